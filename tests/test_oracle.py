@@ -1,0 +1,92 @@
+"""The oracle against its pins (CPU only)."""
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+
+def test_sft_bruteforce_dft():
+    pins.check_sft_bruteforce(oracle.build_sfts)
+
+
+def test_sft_parseval():
+    pins.check_sft_parseval(oracle.build_sfts)
+
+
+def test_sft_sinusoid_closed_form():
+    pins.check_sft_sinusoid(oracle.build_sfts)
+
+
+def test_sft_noise_exp1_and_gamma():
+    pins.check_sft_noise_law(oracle.build_sfts)
+
+
+def test_noise_gamma_through_statistic():
+    pins.check_sft_noise_law(oracle.build_sfts, oracle.score_tracks)
+
+
+def test_basis_identities():
+    pins.check_basis_identities(oracle.build_basis)
+
+
+def test_basis_full_rank():
+    pins.check_basis_full_rank(oracle.build_basis)
+
+
+def test_basis_rank_one_closed_form():
+    pins.check_basis_rank_one(oracle.build_basis)
+
+
+def test_basis_low_rank_recovery():
+    pins.check_basis_low_rank_recovery(oracle.build_basis)
+
+
+def test_score_exact_bruteforce():
+    pins.check_score_exact(oracle.score_tracks)
+
+
+def test_score_exact_matches_fraction_oracle():
+    for seed in range(3):
+        P, f0, U, C, t = pins.tiny_score_case(seed)
+        s_exact, b_exact = oracle.score_tracks_exact(P, f0, U, C, t)
+        got = oracle.score_tracks(P, f0, U, C, t, 0, want_bins=True)
+        assert np.array_equal(got["bins"], b_exact)
+        assert np.allclose(got["stat"], s_exact, rtol=1e-15, atol=0)
+
+
+def test_score_near_ties_large():
+    pins.check_score_near_ties_large(oracle.score_tracks)
+
+
+def test_score_half_even():
+    pins.check_score_half_even(oracle.score_tracks)
+
+
+def test_score_column_sum():
+    pins.check_score_column_sum(oracle.score_tracks)
+
+
+def test_score_permutation_and_topk():
+    pins.check_score_permutation_and_topk(oracle.score_tracks)
+
+
+def test_score_range_and_nonfinite():
+    pins.check_score_range(oracle.score_tracks)
+
+
+def test_oracle_is_isolated():
+    """The oracle imports nothing from the HIP library package."""
+    import ast, pathlib
+    root = pathlib.Path(oracle.__file__).parent
+    for path in root.glob("*.py"):
+        tree = ast.parse(path.read_text())
+        for node in ast.walk(tree):
+            names = []
+            if isinstance(node, ast.Import):
+                names = [a.name for a in node.names]
+            elif isinstance(node, ast.ImportFrom) and node.module:
+                names = [node.module]
+            for n in names:
+                assert not n.startswith("paper_2510_20891_amd"), path
+                assert not n.startswith("synth"), path

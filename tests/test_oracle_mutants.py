@@ -1,0 +1,171 @@
+"""Plant plausible mistakes in the oracle (CPU only) and check that a pin catches each.
+
+Every mutant patches one step of the oracle module in place (monkeypatch undoes
+it afterwards); the pins must then fail.  This shows the pins are sharp enough
+that a dropped term, wrong sign, shifted index or transposed operand in the
+oracle would not go unnoticed.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.basis as ob
+import oracle.score as osc
+import oracle.sft as osft
+from tests import pins
+
+SFT_PINS = [pins.check_sft_bruteforce, pins.check_sft_parseval, pins.check_sft_sinusoid,
+            pins.check_sft_noise_law]
+BASIS_PINS = [pins.check_basis_identities, pins.check_basis_full_rank, pins.check_basis_rank_one,
+              pins.check_basis_low_rank_recovery]
+SCORE_PINS = [pins.check_score_exact, pins.check_score_near_ties_large, pins.check_score_half_even, pins.check_score_column_sum,
+              pins.check_score_permutation_and_topk, pins.check_score_range]
+
+
+def _caught(checks, fn):
+    for check in checks:
+        try:
+            check(fn)
+        except (AssertionError, ValueError, IndexError):
+            return True
+    return False
+
+
+SFT_MUTANTS = {
+    "no_window": ("hann_periodic", lambda n: np.ones(n)),
+    "symmetric_hann": ("hann_periodic", lambda n: np.sin(np.pi * np.arange(n) / (n - 1)) ** 2),
+    "window_shifted": ("hann_periodic", lambda n: np.sin(np.pi * (np.arange(n) + 0.5) / n) ** 2),
+    "norm_missing_2": ("normaliser", lambda w, psd, dt: np.sum(w * w) * psd / dt),
+    "norm_sum_w": ("normaliser", lambda w, psd, dt: np.sum(w) * psd / (2.0 * dt)),
+    "psd_shifted": ("normaliser", lambda w, psd, dt: np.sum(w * w) * np.roll(psd, 1) / (2.0 * dt)),
+    "segments_interleaved": ("segments",
+                             lambda x, n: x[: (x.size // n) * n].reshape(n, x.size // n).T),
+    "segments_overlap_start": ("segments",
+                               lambda x, n: np.stack([x[a * n + 1:(a + 1) * n + 1]
+                                                      for a in range(x.size // n - 1)] +
+                                                     [x[(x.size // n - 1) * n:(x.size // n) * n]])),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SFT_MUTANTS))
+def test_sft_mutant_caught(name, monkeypatch):
+    attr, fn = SFT_MUTANTS[name]
+    monkeypatch.setattr(osft, attr, fn)
+    assert _caught(SFT_PINS, osft.build_sfts), name
+
+
+def _svd_off_by_one(X, K):
+    _, s, vt = np.linalg.svd(X, full_matrices=False)
+    return vt[1:K + 1].T.copy(), s[1:]
+
+
+def _svd_left_padded(X, K):
+    u, s, vt = np.linalg.svd(X, full_matrices=False)
+    V = vt[:K].T.copy()
+    return V[::-1].copy(), s
+
+
+BASIS_MUTANTS = {
+    "uncentred": ("centre_tracks", lambda F: (np.zeros(F.shape[1]), F)),
+    "centre_median": ("centre_tracks", lambda F: (np.median(F, axis=0), F - np.median(F, axis=0))),
+    "component_off_by_one": ("leading_right_vectors", _svd_off_by_one),
+    "segments_reversed": ("leading_right_vectors", _svd_left_padded),
+    "no_sign_rule": ("apply_sign_rule", lambda U: -U),
+    "box_mean_3std": ("coefficient_box", lambda C: (C.mean(0) - 3 * C.std(0), C.mean(0) + 3 * C.std(0))),
+    "box_nearest": ("coefficient_box", lambda C: (np.quantile(C, 0.00135, axis=0, method="nearest"),
+                                                  np.quantile(C, 0.99865, axis=0, method="nearest"))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BASIS_MUTANTS))
+def test_basis_mutant_caught(name, monkeypatch):
+    attr, fn = BASIS_MUTANTS[name]
+    monkeypatch.setattr(ob, attr, fn)
+    assert _caught(BASIS_PINS, ob.build_basis), name
+
+
+_orig_positions = osc.track_positions
+_orig_bins = osc.chosen_bins
+
+
+def _pos_no_f0(f0, U, c, t):
+    return _orig_positions(np.zeros_like(np.asarray(f0, dtype=np.float64)), U, c, t)
+
+
+def _pos_no_T(f0, U, c, t):
+    return _orig_positions(f0, U, c, 1.0) * 1.0
+
+
+def _pos_U_reversed(f0, U, c, t):
+    return _orig_positions(f0, np.asarray(U)[::-1], c, t)
+
+
+def _pos_sign(f0, U, c, t):
+    return _orig_positions(f0, -np.asarray(U, dtype=np.float64), c, t)
+
+
+def _pos_fp32(f0, U, c, t):
+    return _orig_positions(f0, U, c, t).astype(np.float32).astype(np.float64)
+
+
+def _bins_floor(x, n_bins, k_min=0, k_max=None):
+    return _orig_bins(np.floor(x), n_bins, k_min, k_max)
+
+
+def _bins_half_up(x, n_bins, k_min=0, k_max=None):
+    return _orig_bins(np.floor(x + 0.5), n_bins, k_min, k_max)
+
+
+def _bins_clamped(x, n_bins, k_min=0, k_max=None):
+    k_max = n_bins - 1 if k_max is None else k_max
+    xs = np.where(np.isfinite(x), x, 0.0)
+    b = np.clip(np.rint(xs), k_min, k_max).astype(np.int64)
+    return b, np.isfinite(x)
+
+
+def _bins_off_by_one_range(x, n_bins, k_min=0, k_max=None):
+    return _orig_bins(x, n_bins + 1, k_min, None if k_max is None else k_max + 1)
+
+
+def _topk_desc_index(stat, top_k):
+    stat = np.asarray(stat, dtype=np.float64)
+    n = stat.size
+    order = np.lexsort((-np.arange(n), -stat))[: min(top_k, n)]
+    vals = np.full(top_k, -np.inf)
+    idx = np.full(top_k, -1, dtype=np.int64)
+    vals[: order.size] = stat[order]
+    idx[: order.size] = order
+    return vals, idx
+
+
+def _topk_ascending(stat, top_k):
+    stat = np.asarray(stat, dtype=np.float64)
+    n = stat.size
+    order = np.lexsort((np.arange(n), stat))[: min(top_k, n)]
+    vals = np.full(top_k, -np.inf)
+    idx = np.full(top_k, -1, dtype=np.int64)
+    vals[: order.size] = stat[order]
+    idx[: order.size] = order
+    return vals, idx
+
+
+SCORE_MUTANTS = {
+    "dropped_f0": ("track_positions", _pos_no_f0),
+    "missing_T": ("track_positions", _pos_no_T),
+    "segments_reversed": ("track_positions", _pos_U_reversed),
+    "basis_sign": ("track_positions", _pos_sign),
+    "fp32_positions": ("track_positions", _pos_fp32),
+    "floor": ("chosen_bins", _bins_floor),
+    "half_up": ("chosen_bins", _bins_half_up),
+    "clamped_edges": ("chosen_bins", _bins_clamped),
+    "range_off_by_one": ("chosen_bins", _bins_off_by_one_range),
+    "topk_tiebreak": ("topk_order", _topk_desc_index),
+    "topk_ascending": ("topk_order", _topk_ascending),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SCORE_MUTANTS))
+def test_score_mutant_caught(name, monkeypatch):
+    attr, fn = SCORE_MUTANTS[name]
+    monkeypatch.setattr(osc, attr, fn)
+    assert _caught(SCORE_PINS, osc.score_tracks), name
