@@ -1,0 +1,176 @@
+/*
+ * emri.h -- C ABI of the MI355X (gfx950) library for the semi-coherent
+ * single-harmonic EMRI track search (arXiv 2510.20891).
+ *
+ * The library builds a PSD-normalised SFT power spectrogram from a time series,
+ * builds an SVD basis of frequency tracks, and scores very large batches of
+ * basis-coefficient vectors against the spectrogram: every track is rebuilt at
+ * every segment midpoint, the power in its nearest frequency bin is looked up,
+ * the lookups are summed over segments and the best tracks are kept (top-k).
+ *
+ * Conventions shared by every call
+ *   - Plain C types only.  Pointers documented as "device" point to GPU memory
+ *     (for instance a PyTorch tensor's data_ptr()); "host" pointers to CPU memory.
+ *   - Every buffer, including the scoring workspace, is allocated by the caller.
+ *     The library never allocates device memory and never synchronises a stream:
+ *     device calls only enqueue work on `hip_stream` (a hipStream_t; NULL is the
+ *     default stream) and return.  Outputs are valid once the caller has
+ *     synchronised that stream.
+ *   - Every call returns an emri_status.  Arguments are validated before any HIP
+ *     call; on failure nothing is enqueued and emri_last_error() describes why.
+ *     Nothing is thrown or aborted across the boundary.
+ *   - Device pointers must be 16-byte aligned.
+ */
+#ifndef EMRI_H
+#define EMRI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  EMRI_OK = 0,
+  EMRI_EINVAL = -1,       /* a NULL required pointer, a size or value out of range */
+  EMRI_ERANGE = -2,       /* a size product overflows                             */
+  EMRI_ENOMEM = -3,       /* the workspace passed is smaller than required        */
+  EMRI_EDEVICE = -4,      /* a HIP call or kernel launch failed                   */
+  EMRI_EUNSUPPORTED = -5  /* a valid request this build does not implement        */
+} emri_status;
+
+typedef enum { EMRI_F32 = 0, EMRI_F16 = 1 } emri_pdtype;   /* power storage type */
+
+/* A normalised-power spectrogram in device memory, owned by the caller.
+ * Row alpha (segment alpha) holds P[alpha, b] for bins b = 0..n_bins-1 at
+ * data[alpha * row_pitch + b]; elements n_bins..row_pitch-1 of a row are padding
+ * that scoring never reads as power.  row_pitch is a multiple of 8 elements and
+ * at least n_bins; data is 16-byte aligned. */
+typedef struct {
+  void *data;
+  int32_t n_seg;          /* number of segments (rows)                                  */
+  int32_t n_bins;         /* bins per row = n_sft/2 + 1                                  */
+  int32_t row_pitch;      /* elements between consecutive rows                           */
+  int32_t dtype;          /* emri_pdtype                                                 */
+  double t_sft;           /* segment duration T_SFT in seconds; bin b is at b / T_SFT Hz */
+} emri_power;
+
+/* Options for score_tracks; a NULL pointer selects the defaults. */
+typedef struct {
+  int32_t k_min;          /* lowest bin that contributes (default 0)                      */
+  int32_t k_max;          /* highest bin that contributes; < 0 means n_bins - 1 (default) */
+  int32_t reserved[6];    /* must be zero                                                 */
+} score_opts;
+
+/*
+ * build_sfts -- normalised SFT power of a real time series.
+ *
+ * Sec. II B cuts the data into SFT segments of duration T_SFT (bin width
+ * 1/T_SFT) and weights every bin by the inverse PSD (Eq. (7)); Sec. II F takes
+ * the PSD as known.  Segment alpha is samples [alpha*n_sft, (alpha+1)*n_sft) of
+ * x (n_seg = n_samples / n_sft; trailing samples are dropped).  Each segment is
+ * multiplied by the periodic Hann window w_n = sin^2(pi n / n_sft), transformed
+ * with a real DFT (FP64, computed on the GPU), and
+ *     P[alpha, b] = |X_b|^2 / ((3 n_sft / 8) * psd[b] / (2 dt)),
+ * where 3 n_sft / 8 = sum_n w_n^2.  Bins whose psd is non-positive or not finite
+ * get P = 0.  With this normalisation noise-only power is Exp(1) distributed.
+ *
+ *   x          device FP64[n_samples]
+ *   dt         sample spacing in seconds (finite, > 0)
+ *   n_sft      samples per segment: even, >= 4, n_sft/2 with no prime factor
+ *              above 7, and n_sft <= 20480 (EMRI_EUNSUPPORTED otherwise)
+ *   psd        device FP64[n_sft/2 + 1], one-sided PSD at f_b = b / (n_sft dt)
+ *   out        caller-owned spectrogram: out->data (device, n_seg*row_pitch
+ *              elements), out->row_pitch and out->dtype are read; n_seg, n_bins
+ *              and t_sft are written.  Padding elements are written as 0.
+ *              FP16 storage rounds to nearest (values above the FP16 range
+ *              become +inf).
+ */
+int build_sfts(const double *x, int64_t n_samples, double dt, int32_t n_sft,
+               const double *psd, emri_power *out, void *hip_stream);
+
+/*
+ * build_basis -- centred SVD basis of training frequency tracks (host, FP64,
+ * synchronous; no GPU involved).
+ *
+ * Sec. II C factorises the matrix of training tracks with the SVD (Eq. (9)) and
+ * writes a track as a combination of leading singular vectors (Eq. (10)); the
+ * coefficient prior is uniform within symmetric 3-sigma quantiles.  Here
+ *   f0[alpha]    = mean over training tracks (the basis is centred),
+ *   U[:, k]      = k-th right singular vector of the centred matrix, k < K,
+ *                  sign chosen so that its largest-magnitude entry is positive
+ *                  (lowest alpha on a tie),
+ *   sv[k]        = k-th singular value (descending),
+ *   box_lo/hi[k] = 0.135 % / 99.865 % quantiles (linear interpolation) of the
+ *                  training projections (F - f0) U[:, k].
+ * A track is then f(t_alpha) = f0[alpha] + sum_k c_k U[alpha, k].
+ *
+ *   tracks   host FP64[n_train * n_seg], row-major (one training track per row), Hz
+ *   K        0 <= K <= min(n_train, n_seg)
+ *   f0       host FP64[n_seg];  U host FP64[n_seg * K] row-major (U[alpha*K + k])
+ *   sv, box_lo, box_hi   host FP64[K]
+ */
+int build_basis(const double *tracks, int64_t n_train, int32_t n_seg, int32_t K,
+                double *f0, double *U, double *sv, double *box_lo, double *box_hi);
+
+/*
+ * score_tracks_workspace_size -- bytes of device workspace score_tracks needs
+ * for these sizes (stat == NULL needs room for the statistic as well).
+ */
+int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tmpl,
+                                int32_t top_k, int32_t stat_in_workspace, size_t *bytes);
+
+/*
+ * score_tracks -- nearest-bin semi-coherent statistic and top-k of a batch.
+ *
+ * Eq. (6) sums the per-segment statistic over segments; for a template that
+ * occupies one bin per segment (the zero-bandwidth limit of the linear-chirp
+ * template of Sec. II B) the per-segment term is the normalised power in that
+ * bin.  With tracks rebuilt by the matrix product of Eq. (10):
+ *     x[j, alpha] = (f0[alpha] + sum_k c[j, k] U[alpha, k]) * T_SFT   (FP64)
+ *     b[j, alpha] = rint(x[j, alpha])          (round half to even)
+ *     S[j]        = sum over alpha with k_min <= b <= k_max of P[alpha, b]
+ * Non-finite positions contribute nothing.  Positions are evaluated in FP64
+ * (f0 T_SFT + sum_k c_k (U T_SFT) with fused multiply-adds), so chosen bins
+ * agree with any FP64 evaluation except within ~1e-12 bin of a half-integer.
+ * The statistic is accumulated in FP32 over runs of 8 segments and in FP64
+ * across runs (relative error below 1e-6), and stored as FP32.  Sec. II D
+ * keeps the best candidates of a batch: the top-k is ordered by decreasing S
+ * and then increasing template index; NaN statistics rank below every number.
+ *
+ *   power      spectrogram (FP32 or FP16), device
+ *   f0         device FP64[n_seg]; U device FP64[n_seg * K] row-major
+ *   K          0..32
+ *   coeffs     device FP32[n_tmpl * K] row-major (one template per row)
+ *   n_tmpl     0 <= n_tmpl <= 2^31 - 1
+ *   top_k      0..4096
+ *   stat       device FP32[n_tmpl] or NULL (then the workspace holds it)
+ *   topk_val   device FP32[top_k]; topk_idx device INT64[top_k]; entries past
+ *              n_tmpl are (-inf, -1).  Both may be NULL when top_k == 0.
+ *   bins       device INT32[n_tmpl * n_seg] or NULL: if given, the chosen bin of
+ *              every (template, segment), -1 where it does not contribute.
+ *   n_near_tie device INT64[1] or NULL: if given, set to the number of
+ *              (template, segment) positions within 1e-6 bin of a half-integer.
+ *   (bins and n_near_tie select a slower validation kernel.)
+ *   opts       NULL or bin range options
+ *   workspace  device, at least score_tracks_workspace_size() bytes, 256-byte
+ *              aligned; its contents on entry are irrelevant.
+ */
+int score_tracks(const emri_power *power, const double *f0, const double *U, int32_t K,
+                 const float *coeffs, int64_t n_tmpl, int32_t top_k,
+                 float *stat, float *topk_val, int64_t *topk_idx,
+                 int32_t *bins, int64_t *n_near_tie, const score_opts *opts,
+                 void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/* Human-readable name of a status code (static storage). */
+const char *emri_status_string(int status);
+
+/* Detail of the last failing call on this thread ("" if none; thread-local storage). */
+const char *emri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EMRI_H */

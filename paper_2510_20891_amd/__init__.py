@@ -1,0 +1,248 @@
+"""Python binding of libemri.so: the MI355X (gfx950) semi-coherent EMRI track search.
+
+Argument marshalling only.  Every step of the path runs in the library's HIP
+kernels (or, for build_basis, its host C++); PyTorch supplies device memory and
+the current HIP stream.  The functions mirror the C ABI in include/emri.h:
+
+    build_sfts(x, dt, n_sft, psd)            -> Spectrogram
+    build_basis(tracks, K)                   -> (f0, U, sv, box_lo, box_hi)
+    score_tracks(spec, f0, U, coeffs, top_k) -> dict(stat, topk_val, topk_idx, ...)
+
+There is no fallback: if the shared library is missing, or a call fails, an
+exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libemri.so")
+
+F32, F16 = 0, 1
+_DTYPES = {"f32": F32, "f16": F16}
+MAX_K = 32
+MAX_TOPK = 4096
+
+_lib = None
+
+
+class EmriError(RuntimeError):
+    def __init__(self, func: str, status: int, detail: str):
+        super().__init__(f"{func} failed with status {status}: {detail}")
+        self.status = status
+
+
+class _Power(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("n_seg", ctypes.c_int32), ("n_bins", ctypes.c_int32),
+                ("row_pitch", ctypes.c_int32), ("dtype", ctypes.c_int32), ("t_sft", ctypes.c_double)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+_vp, _i32, _i64, _dbl, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+
+SIGNATURES = {
+    "build_sfts": (ctypes.c_int, [_vp, _i64, _dbl, _i32, _vp, ctypes.POINTER(_Power), _vp]),
+    "build_basis": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "score_tracks_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Power), _i32, _i64, _i32, _i32,
+                                                   ctypes.POINTER(_sz)]),
+    "score_tracks": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp,
+                                    _vp, _vp, ctypes.POINTER(_Opts), _vp, _sz, _vp]),
+    "emri_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "emri_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libemri.so (built in place by paper_2510_20891_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2510_20891_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(func: str, status: int) -> None:
+    if status != 0:
+        lib = load()
+        raise EmriError(func, status, lib.emri_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _require_cuda(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+@dataclass
+class Spectrogram:
+    """Normalised power P[alpha, b] in device memory: ``data`` is (n_seg, row_pitch)."""
+    data: "object"          # torch.Tensor, float32 or float16
+    n_bins: int
+    t_sft: float
+
+    @property
+    def n_seg(self) -> int:
+        return int(self.data.shape[0])
+
+    @property
+    def row_pitch(self) -> int:
+        return int(self.data.shape[1])
+
+    @property
+    def dtype_code(self) -> int:
+        import torch
+        return F16 if self.data.dtype == torch.float16 else F32
+
+    def power(self):
+        """The (n_seg, n_bins) view of the power without row padding."""
+        return self.data[:, : self.n_bins]
+
+    def _struct(self) -> _Power:
+        return _Power(self.data.data_ptr() if self.data.numel() else 0, self.n_seg, self.n_bins,
+                      self.row_pitch, self.dtype_code, float(self.t_sft))
+
+
+def default_row_pitch(n_bins: int) -> int:
+    return (n_bins + 7) // 8 * 8
+
+
+def spectrogram_from_power(power, t_sft: float, dtype: str = "f32"):
+    """Wrap an (n_seg, n_bins) host or device array as a padded device Spectrogram."""
+    import torch
+    p = torch.as_tensor(power)
+    n_seg, n_bins = p.shape
+    tdtype = torch.float32 if dtype == "f32" else torch.float16
+    data = torch.zeros((n_seg, default_row_pitch(n_bins)), dtype=tdtype, device="cuda")
+    data[:, :n_bins] = p.to(device="cuda", dtype=tdtype)
+    return Spectrogram(data, n_bins, float(t_sft))
+
+
+def build_sfts(x, dt: float, n_sft: int, psd, dtype: str = "f32", row_pitch: int | None = None,
+               stream=None) -> Spectrogram:
+    """Normalised SFT power of a device FP64 time series (see include/emri.h)."""
+    import torch
+    _require_cuda(x, torch.float64, "x")
+    _require_cuda(psd, torch.float64, "psd")
+    n_bins = n_sft // 2 + 1
+    n_seg = x.numel() // n_sft if n_sft > 0 else 0
+    pitch = row_pitch or default_row_pitch(n_bins)
+    tdtype = torch.float32 if dtype == "f32" else torch.float16
+    data = torch.empty((n_seg, pitch), dtype=tdtype, device=x.device)
+    pw = _Power(data.data_ptr() if data.numel() else 0, 0, 0, pitch, _DTYPES[dtype], 0.0)
+    _check("build_sfts", load().build_sfts(_ptr(x), x.numel(), float(dt), int(n_sft), _ptr(psd),
+                                           ctypes.byref(pw), _stream(stream)))
+    assert pw.n_seg == n_seg and pw.n_bins == n_bins
+    return Spectrogram(data, n_bins, pw.t_sft)
+
+
+def build_basis(tracks, K: int):
+    """Centred SVD basis of training tracks (host, FP64): (f0, U, sv, box_lo, box_hi)."""
+    F = np.ascontiguousarray(tracks, dtype=np.float64)
+    n_train, n_seg = F.shape
+    f0 = np.empty(n_seg)
+    U = np.empty((n_seg, K))
+    sv, lo, hi = np.empty(K), np.empty(K), np.empty(K)
+    p = lambda a: a.ctypes.data if a.size else None
+    _check("build_basis", load().build_basis(F.ctypes.data, n_train, n_seg, int(K), f0.ctypes.data, p(U),
+                                             p(sv), p(lo), p(hi)))
+    return f0, U, sv, lo, hi
+
+
+def score_tracks_workspace_size(spec: Spectrogram, K: int, n_tmpl: int, top_k: int,
+                                stat_in_workspace: bool) -> int:
+    out = ctypes.c_size_t(0)
+    pw = spec._struct()
+    _check("score_tracks_workspace_size",
+           load().score_tracks_workspace_size(ctypes.byref(pw), int(K), int(n_tmpl), int(top_k),
+                                              int(bool(stat_in_workspace)), ctypes.byref(out)))
+    return int(out.value)
+
+
+class Workspace:
+    """A reusable device workspace that grows on demand."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
+            self.buf = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        off = (-base) % 256
+        return base + off, self.buf.numel() - off
+
+
+_default_ws = Workspace()
+
+
+def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: bool = True,
+                 want_bins: bool = False, want_near_tie: bool = False, k_min: int = 0, k_max: int = -1,
+                 out: dict | None = None, workspace: Workspace | None = None, stream=None) -> dict:
+    """Nearest-bin statistic and top-k of a coefficient batch (device tensors).
+
+    f0: (n_seg,) float64;  U: (n_seg, K) float64;  coeffs: (n_tmpl, K) float32.
+    Returns tensors: ``stat`` (n_tmpl,) float32 if want_stat, ``topk_val`` (top_k,),
+    ``topk_idx`` (top_k,) int64, and ``bins`` / ``n_near_tie`` if requested.
+    ``out`` may hold preallocated tensors under the same keys.
+    """
+    import torch
+    _require_cuda(f0, torch.float64, "f0")
+    _require_cuda(U, torch.float64, "U")
+    _require_cuda(coeffs, torch.float32, "coeffs")
+    K = int(U.shape[1]) if U.dim() == 2 else 0
+    n_tmpl = int(coeffs.shape[0])
+    if coeffs.dim() != 2 or coeffs.shape[1] != K:
+        raise ValueError("coeffs must be (n_tmpl, K)")
+    dev = coeffs.device
+    out = {} if out is None else out
+    res = {}
+    if want_stat:
+        res["stat"] = out.get("stat") if out.get("stat") is not None else torch.empty(n_tmpl, dtype=torch.float32, device=dev)
+    res["topk_val"] = out.get("topk_val") if out.get("topk_val") is not None else torch.empty(top_k, dtype=torch.float32, device=dev)
+    res["topk_idx"] = out.get("topk_idx") if out.get("topk_idx") is not None else torch.empty(top_k, dtype=torch.int64, device=dev)
+    if want_bins:
+        res["bins"] = torch.empty((n_tmpl, spec.n_seg), dtype=torch.int32, device=dev)
+    if want_near_tie:
+        res["n_near_tie"] = torch.zeros(2, dtype=torch.int64, device=dev)
+    nbytes = score_tracks_workspace_size(spec, K, n_tmpl, top_k, not want_stat)
+    ws_ptr, ws_len = (workspace or _default_ws).get(nbytes, dev)
+    opts = _Opts(int(k_min), int(k_max))
+    pw = spec._struct()
+    _check("score_tracks", load().score_tracks(
+        ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, int(top_k),
+        _ptr(res.get("stat")), _ptr(res["topk_val"]) if top_k else None,
+        _ptr(res["topk_idx"]) if top_k else None, _ptr(res.get("bins")),
+        _ptr(res.get("n_near_tie")), ctypes.byref(opts), ws_ptr, ws_len, _stream(stream)))
+    return res
+
+
+__all__ = ["load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+           "Spectrogram", "spectrogram_from_power", "Workspace", "EmriError", "F32", "F16", "LIB_PATH"]

@@ -1,0 +1,171 @@
+// C ABI of score_tracks: argument validation, workspace layout and launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.h"
+#include "score_internal.h"
+
+using namespace emri;
+
+namespace {
+
+constexpr size_t kLdsLimit = 163840;      // bytes of LDS a gfx950 workgroup may use
+
+struct Layout {
+  size_t seg_off, bound_off, stat_off, topk_off, total;
+  int seg_stride;
+};
+
+int elem_bytes(int dtype) { return dtype == EMRI_F16 ? 2 : 4; }
+
+int check_power(const emri_power *pw) {
+  if (!pw) return fail(EMRI_EINVAL, "power is NULL");
+  if (pw->dtype != EMRI_F32 && pw->dtype != EMRI_F16) return fail(EMRI_EINVAL, "unknown power dtype %d", pw->dtype);
+  if (pw->n_seg < 0 || pw->n_bins < 1) return fail(EMRI_EINVAL, "n_seg must be >= 0 and n_bins >= 1");
+  if (pw->row_pitch < pw->n_bins || (pw->row_pitch % 8) != 0)
+    return fail(EMRI_EINVAL, "row_pitch %d must be a multiple of 8 and >= n_bins %d", pw->row_pitch, pw->n_bins);
+  if (!std::isfinite(pw->t_sft) || !(pw->t_sft > 0.0)) return fail(EMRI_EINVAL, "t_sft must be finite and > 0");
+  if ((int64_t)pw->row_pitch * elem_bytes(pw->dtype) > INT32_MAX) return fail(EMRI_ERANGE, "row too long");
+  return EMRI_OK;
+}
+
+int make_layout(const emri_power *pw, int K, int64_t n_tmpl, int top_k, bool stat_in_ws, Layout *L) {
+  L->seg_stride = (K + 2) & ~1;                  // f0T + K entries, even for 16-byte rows
+  size_t off = 0;
+  L->seg_off = off;
+  off += round_up((size_t)(pw->n_seg > 0 ? pw->n_seg : 1) * L->seg_stride * sizeof(double), 256);
+  L->bound_off = off;
+  off += round_up((EMRI_MAX_K + 1) * sizeof(double), 256);
+  L->stat_off = off;
+  if (stat_in_ws) off += round_up((size_t)n_tmpl * sizeof(float), 256);
+  L->topk_off = off;
+  off += topk_workspace_bytes(top_k);
+  L->total = off;
+  return EMRI_OK;
+}
+
+int check_sizes(const emri_power *pw, int K, int64_t n_tmpl, int top_k) {
+  int st = check_power(pw);
+  if (st) return st;
+  if (K < 0 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K = %d outside [0, %d]", K, EMRI_MAX_K);
+  if (n_tmpl < 0 || n_tmpl > INT32_MAX) return fail(EMRI_EINVAL, "n_tmpl = %lld outside [0, 2^31-1]", (long long)n_tmpl);
+  if (top_k < 0 || top_k > EMRI_MAX_TOPK) return fail(EMRI_EINVAL, "top_k = %d outside [0, %d]", top_k, EMRI_MAX_TOPK);
+  if ((int64_t)pw->n_seg * n_tmpl > (int64_t)1 << 62) return fail(EMRI_ERANGE, "n_tmpl * n_seg overflows");
+  return EMRI_OK;
+}
+
+}  // namespace
+
+extern "C" int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tmpl, int32_t top_k,
+                                           int32_t stat_in_workspace, size_t *bytes) {
+  clear_error();
+  if (!bytes) return fail(EMRI_EINVAL, "bytes is NULL");
+  int st = check_sizes(power, K, n_tmpl, top_k);
+  if (st) return st;
+  Layout L;
+  make_layout(power, K, n_tmpl, top_k, stat_in_workspace != 0, &L);
+  *bytes = L.total;
+  return EMRI_OK;
+}
+
+extern "C" int score_tracks(const emri_power *power, const double *f0, const double *U, int32_t K,
+                            const float *coeffs, int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val,
+                            int64_t *topk_idx, int32_t *bins, int64_t *n_near_tie, const score_opts *opts,
+                            void *workspace, size_t workspace_bytes, void *hip_stream) {
+  clear_error();
+  int st = check_sizes(power, K, n_tmpl, top_k);
+  if (st) return st;
+  int k_min = 0, k_max = power->n_bins - 1;
+  if (opts) {
+    for (int i = 0; i < 6; ++i)
+      if (opts->reserved[i] != 0) return fail(EMRI_EINVAL, "score_opts.reserved must be zero");
+    k_min = opts->k_min;
+    if (opts->k_max >= 0) k_max = opts->k_max;
+  }
+  if (k_min < 0 || k_max > power->n_bins - 1 || k_min > k_max)
+    return fail(EMRI_EINVAL, "bin range [%d, %d] not inside [0, %d]", k_min, k_max, power->n_bins - 1);
+  if (power->n_seg > 0 && !power->data) return fail(EMRI_EINVAL, "power->data is NULL");
+  if (!f0 && power->n_seg > 0) return fail(EMRI_EINVAL, "f0 is NULL");
+  if (!U && K > 0 && power->n_seg > 0) return fail(EMRI_EINVAL, "U is NULL");
+  if (!coeffs && K > 0 && n_tmpl > 0) return fail(EMRI_EINVAL, "coeffs is NULL");
+  if (top_k > 0 && (!topk_val || !topk_idx)) return fail(EMRI_EINVAL, "topk_val/topk_idx are NULL");
+  if (!workspace) return fail(EMRI_EINVAL, "workspace is NULL");
+  const void *ptrs[] = {power->data, f0, U, coeffs, stat, topk_val, topk_idx, bins, n_near_tie};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(EMRI_EINVAL, "device pointers must be 16-byte aligned");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
+  Layout L;
+  make_layout(power, K, n_tmpl, top_k, stat == nullptr, &L);
+  if (workspace_bytes < L.total)
+    return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
+
+  // LDS staging geometry: a 16-byte lead-in, the row of n_bins elements rounded
+  // up to 16 bytes and copied in 1 KB wave chunks, and a 16-byte tail; two
+  // buffers.  The slots just below k_min and above k_max hold zeros.
+  const int eb = elem_bytes(power->dtype);
+  const int copy_bytes = (int)round_up((size_t)power->n_bins * eb, 16);
+  const int row_chunks = (copy_bytes + 1023) / 1024;
+  const int buf_bytes = SCORE_LDS_LEAD + row_chunks * 1024 + 16;
+  const size_t lds = 2 * (size_t)buf_bytes;
+  if (lds > kLdsLimit)
+    return fail(EMRI_EUNSUPPORTED, "a spectrogram row of %d bins does not fit twice in LDS", power->n_bins);
+  auto owner = [&](int bin) {       // wave whose copy writes bin `bin`, or -1
+    if (bin < 0) return -1;
+    const int chunk = bin * eb / 1024;
+    return chunk < row_chunks ? chunk % (SCORE_THREADS / 64) : -1;
+  };
+  int cus = 0;
+  if ((st = device_cu_count(&cus)) != EMRI_OK) return st;
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  char *ws = reinterpret_cast<char *>(workspace);
+  double *seg = reinterpret_cast<double *>(ws + L.seg_off);
+  double *bound = reinterpret_cast<double *>(ws + L.bound_off);
+  float *stat_buf = stat ? stat : reinterpret_cast<float *>(ws + L.stat_off);
+  const bool validate = bins != nullptr || n_near_tie != nullptr;
+
+  hipError_t err = hipSuccess;
+  if (power->n_seg > 0 || validate) {
+    err = launch_score_prep(f0, U, K, power->n_seg, power->t_sft, (double)eb, seg, L.seg_stride, bound,
+                            reinterpret_cast<unsigned long long *>(n_near_tie), stream);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "score prep launch: %s", hipGetErrorString(err));
+  }
+  if (n_tmpl > 0) {
+    ScoreParams p{};
+    p.power = power->data;
+    p.seg = seg;
+    p.bound = bound;
+    p.coeffs = coeffs;
+    p.stat = stat_buf;
+    p.bins = bins;
+    p.near_tie = reinterpret_cast<unsigned long long *>(n_near_tie);
+    p.n_tmpl = n_tmpl;
+    p.n_seg = power->n_seg;
+    p.seg_stride = L.seg_stride;
+    p.k_min = k_min;
+    p.k_max = k_max;
+    p.row_bytes_pitch = power->row_pitch * eb;
+    p.copy_bytes = copy_bytes;
+    p.row_chunks = row_chunks;
+    p.buf_bytes = buf_bytes;
+    p.lo_owner = owner(k_min - 1);
+    p.hi_owner = owner(k_max + 1);
+    const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;
+    const int grid = (int)(units < cus ? units : cus);
+    p.per_block = (n_tmpl + grid - 1) / grid;
+    if (power->n_seg == 0) {
+      // no segment contributes: every statistic is zero; reuse the validation
+      // kernel, whose segment loop is then empty
+      err = launch_score(p, K, power->dtype, true, grid, lds, stream);
+    } else {
+      err = launch_score(p, K, power->dtype, validate, grid, lds, stream);
+    }
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "score launch: %s", hipGetErrorString(err));
+  }
+  if (top_k > 0) {
+    err = launch_topk(stat_buf, n_tmpl, top_k, topk_val, topk_idx, ws + L.topk_off, cus, stream);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "top-k launch: %s", hipGetErrorString(err));
+  }
+  return EMRI_OK;
+}

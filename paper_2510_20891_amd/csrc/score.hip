@@ -1,0 +1,386 @@
+// score_tracks kernels: track reconstruction, nearest-bin power gather and
+// segment reduction in one pass (Eq. (6) in its nearest-bin limit, tracks from
+// the basis product of Eq. (10), bin width 1/T_SFT of Sec. II B).
+//
+// Layout and schedule (MI355X / gfx950):
+//   * A persistent grid of one 512-thread workgroup per CU.  Workgroup g owns a
+//     contiguous range of templates and walks it in tiles of TPL*512 templates:
+//     lane l holds TPL templates (j = tile + s*512 + l), their K coefficients
+//     widened to FP64 and kept in VGPRs for the whole tile.
+//   * For each segment alpha the power row P[alpha, 0..n_bins) is staged in LDS
+//     by asynchronous global->LDS copies (global_load_lds_dwordx4, 1 KB per wave
+//     instruction) into one of two buffers, so the copy of row alpha+1 overlaps
+//     the gathers from row alpha.  Every workgroup walks the rows in the same
+//     order, so the 32 CUs of an XCD share each row in their L2.
+//   * Per (template, segment), with E = element size in bytes:
+//       y    = E f0T[alpha] + sum_k c_k (E UT[alpha,k])   FP64 fused multiply-adds
+//       off  = low word of (y + M),  M = 1.5*2^52*E + 16 + buffer base
+//       off  = med3(off, lo, hi)                         byte offset of the bin
+//       acc += P at LDS byte off
+//     Scaling by E = 2 or 4 is exact, and adding M rounds y to a multiple of E
+//     with ties to even multiples of 2E, so `off` is 16 + base + E*rint(x) with
+//     rint in round-half-to-even: the FPU's own rounding places the bin, the
+//     buffer base and the row's 16-byte lead-in.  Bins outside [k_min, k_max]
+//     clamp onto the two slots next to the range, which hold zeros.  f0T = f0*T
+//     and UT = U*T are wave-uniform and come from scalar loads.
+//   * The statistic is summed in FP32 over runs of 8 segments and in FP64
+//     across runs; the fixed order makes results independent of the launch.
+//   * Templates whose |x| could reach 2^26 (huge or non-finite coefficients,
+//     non-finite f0/U) are detected per wave from a cheap bound and take a path
+//     that maps such positions (never inside a spectrogram row) to bin -2
+//     before rounding, so they contribute nothing.
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "score_internal.h"
+
+namespace emri {
+
+namespace {
+
+constexpr double kWildLimit = 67108864.0;      // 2^26 (in units of E * bins)
+constexpr double kNearTie = 1e-6;
+constexpr int kLeadIn = SCORE_LDS_LEAD;          // bytes before bin 0 in each LDS buffer
+
+typedef const __attribute__((address_space(4))) double *const_dptr;
+
+typedef __attribute__((address_space(3))) unsigned char lds_byte;
+
+// LDS byte address of a pointer into dynamic shared memory.
+__device__ __forceinline__ int lds_address(const void *p) { return (int)(size_t)(const lds_byte *)p; }
+
+template <typename PT>
+struct Elem;
+template <>
+struct Elem<float> {
+  static constexpr int bytes = 4;
+  __device__ static float load(int addr) { return *(const __attribute__((address_space(3))) float *)(size_t)addr; }
+  __device__ static void zero(int addr) { *(__attribute__((address_space(3))) float *)(size_t)addr = 0.0f; }
+};
+template <>
+struct Elem<__half> {
+  static constexpr int bytes = 2;
+  __device__ static float load(int addr) {
+    const unsigned short h = *(const __attribute__((address_space(3))) unsigned short *)(size_t)addr;
+    return (float)__builtin_bit_cast(_Float16, h);
+  }
+  __device__ static void zero(int addr) {
+    *(__attribute__((address_space(3))) unsigned short *)(size_t)addr = (unsigned short)0;
+  }
+};
+
+// med3 of three signed integers in one VALU instruction (lo in an SGPR, hi in a VGPR).
+__device__ __forceinline__ int clamp_i32(int x, int lo, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(lo), "v"(hi));
+  return r;
+}
+
+// Per-buffer constants of the rounding / addressing step.
+struct BufConst {
+  double magic;
+  int lo, hi;
+};
+
+template <typename PT>
+__device__ __forceinline__ BufConst buffer_consts(const ScoreParams &p, const unsigned char *lds, int buf) {
+  constexpr int E = Elem<PT>::bytes;
+  const int base = lds_address(lds) + buf * p.buf_bytes + kLeadIn;   // absolute LDS byte address of bin 0
+  BufConst bc;
+  bc.magic = 6755399441055744.0 * E + (double)base;     // 1.5*2^52*E + base
+  bc.lo = base + E * (p.k_min - 1);
+  bc.hi = base + E * (p.k_max + 1);
+  return bc;
+}
+
+__device__ __forceinline__ int low_word(double y) { return (int)(unsigned)__double2loint(y); }
+
+// Issue the asynchronous copy of power row `alpha` into LDS buffer `buf`.
+// Every lane copies 16 bytes; lanes past the row re-read its last 16 bytes and
+// write them past the row's end inside the buffer, where no gather looks.
+__device__ __forceinline__ void issue_row_copy(const ScoreParams &p, int alpha, unsigned char *lds, int buf) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const char *src = reinterpret_cast<const char *>(p.power) + (size_t)alpha * (size_t)p.row_bytes_pitch;
+  unsigned char *dst = lds + buf * p.buf_bytes + kLeadIn;
+  for (int c = wave; c < p.row_chunks; c += SCORE_THREADS / 64) {
+    int off = (c * 64 + lane) * 16;
+    off = off < p.copy_bytes ? off : p.copy_bytes - 16;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + off),
+                                     (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void wait_row_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Zero slots just outside [k_min, k_max].  A slot inside the copied part of a
+// row is rewritten after every copy by the wave whose copy covers it; a slot
+// outside it is written once at kernel start.
+template <typename PT>
+__device__ __forceinline__ void zero_slots_after_copy(const ScoreParams &p, unsigned char *lds, int buf) {
+  if ((threadIdx.x & 63) != 0) return;
+  const int wave = threadIdx.x >> 6;
+  if (wave == p.lo_owner) Elem<PT>::zero(buffer_consts<PT>(p, lds, buf).lo);
+  if (wave == p.hi_owner) Elem<PT>::zero(buffer_consts<PT>(p, lds, buf).hi);
+}
+
+__device__ __forceinline__ void init_lds(const ScoreParams &p, unsigned char *lds) {
+  // lead-in and tail of both buffers
+  for (int b = 0; b < 2; ++b) {
+    unsigned char *buf = lds + b * p.buf_bytes;
+    for (int i = threadIdx.x; i < kLeadIn; i += SCORE_THREADS) buf[i] = 0;
+    for (int i = kLeadIn + p.row_chunks * 1024 + threadIdx.x; i < p.buf_bytes; i += SCORE_THREADS) buf[i] = 0;
+  }
+}
+
+// One tile of TPL slots of 512 templates against every segment.
+template <int K, int TPL, typename PT, bool WILD>
+__device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *lds,
+                                         const double (&c)[TPL][K > 0 ? K : 1], double (&sum)[TPL]) {
+  float acc[TPL];
+#pragma unroll
+  for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
+  const BufConst bc0 = buffer_consts<PT>(p, lds, 0), bc1 = buffer_consts<PT>(p, lds, 1);
+  if (p.n_seg > 0) issue_row_copy(p, 0, lds, 0);
+  wait_row_copies();
+  zero_slots_after_copy<PT>(p, lds, 0);
+  __syncthreads();
+  for (int a = 0; a < p.n_seg; ++a) {
+    const int buf = a & 1;
+    if (a + 1 < p.n_seg) issue_row_copy(p, a + 1, lds, buf ^ 1);
+    const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
+    const double f0t = sc[0];
+    double ut[K > 0 ? K : 1];
+#pragma unroll
+    for (int k = 0; k < K; ++k) ut[k] = sc[1 + k];
+    const double magic = buf ? bc1.magic : bc0.magic;
+    const int lo = buf ? bc1.lo : bc0.lo, hi = buf ? bc1.hi : bc0.hi;
+    // All TPL slots are evaluated even in a partial last tile (their lanes hold
+    // zero coefficients and read in-bounds LDS).  Addresses first, then all
+    // gathers, then the sums, so the gathers of one segment overlap.
+    int addr[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      double y = f0t;
+#pragma unroll
+      for (int k = 0; k < K; ++k) y = __builtin_fma(c[s][k], ut[k], y);
+      if constexpr (WILD) y = (__builtin_fabs(y) < kWildLimit) ? y : -2.0 * Elem<PT>::bytes;
+      addr[s] = clamp_i32(low_word(y + magic), lo, hi);
+    }
+    float v[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(addr[s]);
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) acc[s] += v[s];
+    if ((a & 7) == 7 || a + 1 == p.n_seg) {
+#pragma unroll
+      for (int s = 0; s < TPL; ++s) {
+        sum[s] += (double)acc[s];
+        acc[s] = 0.0f;
+      }
+    }
+    wait_row_copies();
+    if (a + 1 < p.n_seg) zero_slots_after_copy<PT>(p, lds, buf ^ 1);
+    __syncthreads();
+  }
+}
+
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  const int tid = threadIdx.x;
+  init_lds(p, lds);
+  const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
+  const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
+  const_dptr bnd_src = (const_dptr)p.bound;
+  double bound_u[K > 0 ? K : 1];
+#pragma unroll
+  for (int k = 0; k < K; ++k) bound_u[k] = bnd_src[1 + k];
+  const double bound_f0 = bnd_src[0];
+  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * SCORE_THREADS) {
+    double c[TPL][K > 0 ? K : 1];
+    bool wild = false;
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+      const bool live = j < j_end;
+      float cf[K > 0 ? K : 1];
+      if constexpr (K % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < K; k += 4) {
+          const float4 v = live ? reinterpret_cast<const float4 *>(p.coeffs + (size_t)j * K)[k / 4]
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+          cf[k] = v.x; cf[k + 1] = v.y; cf[k + 2] = v.z; cf[k + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
+      }
+      double bnd = bound_f0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        c[s][k] = (double)cf[k];
+        bnd += __builtin_fabs(c[s][k]) * bound_u[k];
+      }
+      wild |= !(bnd < 0.5 * kWildLimit);
+    }
+    double sum[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) sum[s] = 0.0;
+    if (__any(wild))
+      run_tile<K, TPL, PT, true>(p, lds, c, sum);
+    else
+      run_tile<K, TPL, PT, false>(p, lds, c, sum);
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+      if (j < j_end) p.stat[j] = (float)sum[s];
+    }
+  }
+}
+
+// Validation variant: one template per lane and runtime K; it also records the
+// chosen bins and counts near-ties.  Same arithmetic and summation order as the
+// fast kernel, so the statistics agree bit for bit.
+template <typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScoreParams p, int K) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  constexpr int E = Elem<PT>::bytes;
+  const int tid = threadIdx.x;
+  init_lds(p, lds);
+  const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
+  const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
+  const BufConst bc0 = buffer_consts<PT>(p, lds, 0), bc1 = buffer_consts<PT>(p, lds, 1);
+  unsigned long long near = 0;
+  for (int64_t t0 = j_begin; t0 < j_end; t0 += SCORE_THREADS) {
+    const int64_t j = t0 + tid;
+    const bool live = j < j_end;
+    double c[EMRI_MAX_K];
+#pragma unroll
+    for (int k = 0; k < EMRI_MAX_K; ++k) c[k] = (k < K && live) ? (double)p.coeffs[(size_t)j * K + k] : 0.0;
+    double sum = 0.0;
+    float acc = 0.0f;
+    if (p.n_seg > 0) issue_row_copy(p, 0, lds, 0);
+    wait_row_copies();
+    zero_slots_after_copy<PT>(p, lds, 0);
+    __syncthreads();
+    for (int a = 0; a < p.n_seg; ++a) {
+      const int buf = a & 1;
+      if (a + 1 < p.n_seg) issue_row_copy(p, a + 1, lds, buf ^ 1);
+      const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
+      double y = sc[0];
+#pragma unroll
+      for (int k = 0; k < EMRI_MAX_K; ++k)
+        if (k < K) y = __builtin_fma(c[k], sc[1 + k], y);
+      const double x = y * (1.0 / E);          // exact: the position in bins
+      if (__builtin_fabs(x) <= 1.7976931348623157e308 && live) {
+        const double fr = x - __builtin_floor(x);
+        if (__builtin_fabs(fr - 0.5) < kNearTie) ++near;
+      }
+      const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0 * E;
+      const BufConst &bc = buf ? bc1 : bc0;
+      const int word = low_word(ys + bc.magic);
+      const int b = (word - (lds_address(lds) + buf * p.buf_bytes + kLeadIn)) / E;
+      acc += Elem<PT>::load(clamp_i32(word, bc.lo, bc.hi));
+      if (live && p.bins) p.bins[(size_t)j * p.n_seg + a] = (b >= p.k_min && b <= p.k_max) ? b : -1;
+      if ((a & 7) == 7 || a + 1 == p.n_seg) {
+        sum += (double)acc;
+        acc = 0.0f;
+      }
+      wait_row_copies();
+      if (a + 1 < p.n_seg) zero_slots_after_copy<PT>(p, lds, buf ^ 1);
+      __syncthreads();
+    }
+    if (live && p.stat) p.stat[j] = (float)sum;
+  }
+  if (p.near_tie && near) atomicAdd(p.near_tie, near);
+}
+
+// Per-segment constants E*f0*T, E*U*T (FP64; E = power element bytes) and the
+// bounds of the wild-template test: bound[0] = max |E f0 T|,
+// bound[1+k] = max_alpha |E U[alpha,k] T| (+inf if an entry is not finite).
+// Also clears the near-tie counter.
+__global__ __launch_bounds__(256) void score_prep_kernel(const double *__restrict__ f0, const double *__restrict__ U,
+                                                         int K, int n_seg, double t_sft, double scale, double *seg,
+                                                         int seg_stride, double *bound, unsigned long long *near_tie) {
+  __shared__ double red[256];
+  if (threadIdx.x == 0 && near_tie) *near_tie = 0ull;
+  for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
+    seg[(size_t)a * seg_stride] = (f0[a] * t_sft) * scale;
+    for (int k = 0; k < K; ++k) seg[(size_t)a * seg_stride + 1 + k] = (U[(size_t)a * K + k] * t_sft) * scale;
+  }
+  for (int col = 0; col <= K; ++col) {
+    double m = 0.0;
+    for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
+      const double v = col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft;
+      const double av = __builtin_fabs(v) * scale;
+      m = (av <= 1.7976931348623157e308) ? (av > m ? av : m) : __builtin_inf();
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bound[col] = red[0];
+    __syncthreads();
+  }
+}
+
+constexpr int tpl_for(int K) {
+  const int t = 180 / (2 * K + 3);
+  return t > 16 ? 16 : (t < 1 ? 1 : t);
+}
+
+template <int K, typename PT>
+hipError_t launch_fast_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
+  constexpr int TPL = tpl_for(K);
+  auto kern = score_fast_kernel<K, TPL, PT>;
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p);
+  return hipGetLastError();
+}
+
+template <typename PT, int... Ks>
+hipError_t dispatch_fast(int K, const ScoreParams &p, int grid, size_t lds, hipStream_t stream,
+                         std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  ((K == Ks ? (err = launch_fast_k<Ks, PT>(p, grid, lds, stream), true) : false) || ...);
+  return err;
+}
+
+template <typename PT>
+hipError_t launch_validate(const ScoreParams &p, int K, int grid, size_t lds, hipStream_t stream) {
+  auto kern = score_validate_kernel<PT>;
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p, K);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int score_templates_per_tile(int K) { return tpl_for(K) * SCORE_THREADS; }
+
+hipError_t launch_score_prep(const double *f0, const double *U, int K, int n_seg, double t_sft, double scale,
+                             double *seg, int seg_stride, double *bound, unsigned long long *near_tie,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(score_prep_kernel, dim3(1), dim3(256), 0, stream, f0, U, K, n_seg, t_sft, scale, seg,
+                     seg_stride, bound, near_tie);
+  return hipGetLastError();
+}
+
+hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, int grid, size_t lds,
+                        hipStream_t stream) {
+  if (validate)
+    return dtype == EMRI_F32 ? launch_validate<float>(p, K, grid, lds, stream)
+                             : launch_validate<__half>(p, K, grid, lds, stream);
+  using Ks = std::make_integer_sequence<int, EMRI_MAX_K + 1>;
+  if (dtype == EMRI_F32) return dispatch_fast<float>(K, p, grid, lds, stream, Ks{});
+  return dispatch_fast<__half>(K, p, grid, lds, stream, Ks{});
+}
+
+}  // namespace emri

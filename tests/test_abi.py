@@ -1,0 +1,156 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and
+rejects invalid arguments before touching the GPU.  build_basis is host code
+and is checked against the oracle here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2510_20891_amd as emri
+from paper_2510_20891_amd import _Opts, _Power
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "emri.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = emri.load()
+    names = declared_functions()
+    assert {"build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+            "emri_status_string", "emri_last_error"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(emri.SIGNATURES)
+
+
+def test_status_strings():
+    lib = emri.load()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.emri_status_string(code)
+    assert b"unknown" in lib.emri_status_string(7)
+
+
+def _power(n_seg=4, n_bins=33, pitch=40, dtype=0, t=100.0, data=0x1000):
+    return _Power(data, n_seg, n_bins, pitch, dtype, t)
+
+
+FAKE = 0x100000   # never dereferenced: validation fails first
+
+
+def _score(pw, K=2, n=10, top_k=4, opts=None, ws_bytes=1 << 20, coeffs=FAKE, ws=FAKE, f0=FAKE, U=FAKE,
+           vals=FAKE, idx=FAKE):
+    lib = emri.load()
+    return lib.score_tracks(ctypes.byref(pw), f0, U, K, coeffs, n, top_k, FAKE, vals, idx, None, None,
+                            ctypes.byref(opts) if opts else None, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(K=33), -1), (dict(K=-1), -1), (dict(n=-1), -1), (dict(top_k=4097), -1), (dict(top_k=-2), -1),
+    (dict(coeffs=None), -1), (dict(ws=None), -1), (dict(vals=None), -1), (dict(f0=None), -1),
+    (dict(coeffs=FAKE + 4), -1), (dict(ws=FAKE + 16), -1), (dict(ws_bytes=64), -3),
+])
+def test_score_tracks_rejects(case, status):
+    assert _score(_power(), **case) == status
+    assert emri.load().emri_last_error()
+
+
+@pytest.mark.parametrize("pw,status", [
+    (_power(pitch=36), -1), (_power(pitch=32), -1), (_power(n_bins=0), -1), (_power(dtype=3), -1),
+    (_power(t=0.0), -1), (_power(t=float("inf")), -1), (_power(data=0), -1), (_power(n_seg=-1), -1),
+    (_power(n_bins=30000, pitch=30000), -5),
+])
+def test_score_tracks_rejects_power(pw, status):
+    assert _score(pw) == status
+
+
+def test_score_tracks_rejects_bin_range():
+    assert _score(_power(), opts=_Opts(5, 2)) == -1
+    assert _score(_power(), opts=_Opts(-1, 3)) == -1
+    assert _score(_power(), opts=_Opts(0, 33)) == -1
+    bad = _Opts(0, -1)
+    bad.reserved[2] = 1
+    assert _score(_power(), opts=bad) == -1
+
+
+def test_workspace_size_grows_with_stat_in_workspace():
+    lib = emri.load()
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    pw = _power()
+    assert lib.score_tracks_workspace_size(ctypes.byref(pw), 8, 1000, 16, 0, ctypes.byref(a)) == 0
+    assert lib.score_tracks_workspace_size(ctypes.byref(pw), 8, 1000, 16, 1, ctypes.byref(b)) == 0
+    assert b.value >= a.value + 4000 and a.value % 256 == 0
+    assert lib.score_tracks_workspace_size(ctypes.byref(pw), 8, 1000, 16, 1, None) == -1
+
+
+def test_build_sfts_rejects():
+    lib = emri.load()
+    pw = _Power(FAKE, 0, 0, 8, 0, 0.0)
+    call = lambda n_sft, dt=1.0, n=1000, pitch=8, x=FAKE, psd=FAKE, dtype=0: lib.build_sfts(
+        x, n, dt, n_sft, psd, ctypes.byref(_Power(FAKE, 0, 0, pitch, dtype, 0.0)), None)
+    assert call(7) == -1                  # odd
+    assert call(2) == -1                  # too short
+    assert call(16, dt=0.0) == -1
+    assert call(16, dt=float("nan")) == -1
+    assert call(16, pitch=4) == -1        # pitch < n_bins
+    assert call(16, pitch=12) == -1       # pitch not a multiple of 8
+    assert call(16, x=None) == -1
+    assert call(16, x=FAKE + 8) == -1     # misaligned
+    assert call(16, dtype=2) == -1
+    assert call(22, pitch=16) == -5       # n_sft/2 = 11: prime factor above 7
+    assert call(40960, pitch=20488) == -5  # beyond the LDS-resident FFT size
+    assert lib.build_sfts(FAKE, 10, 1.0, 16, FAKE, None, None) == -1
+
+
+def test_build_basis_rejects():
+    lib = emri.load()
+    F = np.ones((4, 3))
+    out = np.empty(16)
+    p = out.ctypes.data
+    assert lib.build_basis(F.ctypes.data, 4, 3, 4, p, p, p, p, p) == -1       # K > n_seg
+    assert lib.build_basis(None, 4, 3, 1, p, p, p, p, p) == -1
+    F[1, 1] = np.nan
+    assert lib.build_basis(F.ctypes.data, 4, 3, 1, p, p, p, p, p) == -1
+
+
+def _chirps(n, n_seg, seed, t_sft):
+    g = np.random.default_rng(seed)
+    t = (np.arange(n_seg) + 0.5) * t_sft
+    f0 = g.uniform(1e-3, 2e-2, n)
+    tau = g.uniform(1, 10, n) * 3.15576e7
+    return f0[:, None] * (1 - t[None, :] / tau[:, None]) ** -0.375
+
+
+@pytest.mark.parametrize("n,n_seg,K", [(1000, 30, 4), (5000, 192, 8), (5000, 192, 16), (20, 40, 12)])
+def test_build_basis_matches_oracle(n, n_seg, K):
+    F = _chirps(n, n_seg, 7, 163840.0 if n_seg == 192 else 86400.0)
+    f0, U, sv, lo, hi = emri.build_basis(F, K)
+    of0, oU, osv, olo, ohi = oracle.build_basis(F, K)
+    assert np.allclose(f0, of0, rtol=1e-14, atol=0)
+    assert np.allclose(sv, osv, rtol=1e-9, atol=1e-12 * osv[0])
+    assert np.abs(U.T @ U - np.eye(K)).max() < 1e-12
+    for k in range(K):
+        if osv[k] / osv[0] > 1e-6 and (k + 1 == K or osv[k + 1] < osv[k] * (1 - 1e-6)):
+            assert np.abs(U[:, k] - oU[:, k]).max() < 1e-7, k          # same vector, same sign
+            assert abs(lo[k] - olo[k]) <= 1e-6 * (ohi[k] - olo[k])
+            assert abs(hi[k] - ohi[k]) <= 1e-6 * (ohi[k] - olo[k])
+    # the kept subspace is the same (principal angles)
+    cos = np.linalg.svd(U.T @ oU, compute_uv=False)
+    keep = osv / osv[0] > 1e-6
+    assert np.all(cos[: int(keep.sum())] > 1 - 1e-9)
+
+
+def test_build_basis_full_rank_and_k0():
+    F = _chirps(50, 10, 3, 86400.0)
+    f0, U, sv, lo, hi = emri.build_basis(F, 10)
+    X = F - f0
+    assert np.abs(X @ U @ U.T - X).max() < 1e-12 * np.abs(X).max()
+    f0b, Ub, svb, _, _ = emri.build_basis(F, 0)
+    assert np.allclose(f0b, f0) and Ub.shape == (10, 0)
