@@ -36,6 +36,10 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "score_fast_k8_f32_one_year_tra
 _POOL_STATE = {}
 
 
+def _pool_init(P, f0, U, C, t):
+    _POOL_STATE.update(P=P, f0=f0, U=U, C=C, t=t)
+
+
 def _oracle_chunk(bounds):
     import oracle
     s, e = bounds
@@ -51,17 +55,25 @@ def cpu_baseline(P, f0, U, C, t_sft, n_sample: int) -> dict:
     except AttributeError:
         cores = os.cpu_count() or 1
     cores = max(1, min(cores, 16))
-    _POOL_STATE.update(P=P, f0=f0, U=U, C=C[:n_sample], t=t_sft)
-    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
-        os.environ[var] = "1"
     step = 16384
     chunks = [(s, min(s + step, n_sample)) for s in range(0, n_sample, step)]
-    ctx = mp.get_context("fork")
-    with ctx.Pool(cores) as pool:
+    # fresh worker interpreters (no fork of a process that has loaded the GPU
+    # runtime), each with one BLAS thread: the variables must be set before the
+    # workers import numpy
+    saved = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    for v in saved:
+        os.environ[v] = "1"
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores, initializer=_pool_init, initargs=(P, f0, U, C[:n_sample], t_sft)) as pool:
         pool.map(_oracle_chunk, chunks[:cores])         # warm the workers
         t0 = time.perf_counter()
         pool.map(_oracle_chunk, chunks)
         wall = time.perf_counter() - t0
+    for v, val in saved.items():
+        if val is None:
+            os.environ.pop(v, None)
+        else:
+            os.environ[v] = val
     evals = n_sample * P.shape[0]
     return {"value": evals / wall, "unit": "template-segment evals/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n_sample} of the 1e7 templates x {P.shape[0]} segments, FP64 NumPy oracle, "

@@ -60,9 +60,15 @@ SIGNATURES = {
 
 
 def load():
-    """Load libemri.so (built in place by paper_2510_20891_amd.build)."""
+    """Load libemri.so (built in place by paper_2510_20891_amd.build).
+
+    PyTorch is imported first so that the library binds to the HIP runtime that
+    PyTorch already uses (both carry the soname libamdhip64.so.7): one process,
+    one runtime, shared streams and allocations.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (loads the process's HIP runtime)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2510_20891_amd.build`")
         lib = ctypes.CDLL(LIB_PATH)

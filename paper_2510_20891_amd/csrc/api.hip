@@ -127,7 +127,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
 
   hipError_t err = hipSuccess;
   if (power->n_seg > 0 || validate) {
-    err = launch_score_prep(f0, U, K, power->n_seg, power->t_sft, (double)eb, seg, L.seg_stride, bound,
+    err = launch_score_prep(f0, U, K, power->n_seg, power->t_sft, 1.0, seg, L.seg_stride, bound,
                             reinterpret_cast<unsigned long long *>(n_near_tie), stream);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score prep launch: %s", hipGetErrorString(err));
   }

@@ -12,15 +12,15 @@
 //     instruction) into one of two buffers, so the copy of row alpha+1 overlaps
 //     the gathers from row alpha.  Every workgroup walks the rows in the same
 //     order, so the 32 CUs of an XCD share each row in their L2.
-//   * Per (template, segment), with E = element size in bytes:
-//       y    = E f0T[alpha] + sum_k c_k (E UT[alpha,k])   FP64 fused multiply-adds
-//       off  = low word of (y + M),  M = 1.5*2^52*E + 16 + buffer base
-//       off  = med3(off, lo, hi)                         byte offset of the bin
-//       acc += P at LDS byte off
-//     Scaling by E = 2 or 4 is exact, and adding M rounds y to a multiple of E
-//     with ties to even multiples of 2E, so `off` is 16 + base + E*rint(x) with
-//     rint in round-half-to-even: the FPU's own rounding places the bin, the
-//     buffer base and the row's 16-byte lead-in.  Bins outside [k_min, k_max]
+//   * Per (template, segment), with E = element size in bytes and B = the LDS
+//     byte address of bin 0 of the current buffer:
+//       x    = f0T[alpha] + sum_k c_k UT[alpha,k]        FP64 fused multiply-adds
+//       w    = low word of (x + 1.5*2^52 + B/E)         = B/E + rint(x)
+//       w    = med3(w, B/E + k_min - 1, B/E + k_max + 1)
+//       acc += P at LDS byte address E*w
+//     Adding the constant makes the FPU round x to an integer (half to even,
+//     since B/E is even) and leaves that integer, offset by B/E, in the low
+//     word: the FPU's own rounding places the bin.  Bins outside [k_min, k_max]
 //     clamp onto the two slots next to the range, which hold zeros.  f0T = f0*T
 //     and UT = U*T are wave-uniform and come from scalar loads.
 //   * The statistic is summed in FP32 over runs of 8 segments and in FP64
@@ -39,7 +39,7 @@ namespace emri {
 
 namespace {
 
-constexpr double kWildLimit = 67108864.0;      // 2^26 (in units of E * bins)
+constexpr double kWildLimit = 67108864.0;      // 2^26 bins
 constexpr double kNearTie = 1e-6;
 constexpr int kLeadIn = SCORE_LDS_LEAD;          // bytes before bin 0 in each LDS buffer
 
@@ -77,20 +77,23 @@ __device__ __forceinline__ int clamp_i32(int x, int lo, int hi) {
   return r;
 }
 
-// Per-buffer constants of the rounding / addressing step.
+// Per-buffer constants of the rounding / addressing step (in elements).
 struct BufConst {
   double magic;
   int lo, hi;
+  int base;      // LDS element index (address / E) of bin 0
 };
 
 template <typename PT>
 __device__ __forceinline__ BufConst buffer_consts(const ScoreParams &p, const unsigned char *lds, int buf) {
   constexpr int E = Elem<PT>::bytes;
-  const int base = lds_address(lds) + buf * p.buf_bytes + kLeadIn;   // absolute LDS byte address of bin 0
+  // absolute LDS byte address of bin 0, in elements (even: buffers are 16-byte aligned)
+  const int base = (lds_address(lds) + buf * p.buf_bytes + kLeadIn) / E;
   BufConst bc;
-  bc.magic = 6755399441055744.0 * E + (double)base;     // 1.5*2^52*E + base
-  bc.lo = base + E * (p.k_min - 1);
-  bc.hi = base + E * (p.k_max + 1);
+  bc.base = base;
+  bc.magic = 6755399441055744.0 + (double)base;     // 1.5*2^52 + base
+  bc.lo = base + p.k_min - 1;
+  bc.hi = base + p.k_max + 1;
   return bc;
 }
 
@@ -120,8 +123,8 @@ template <typename PT>
 __device__ __forceinline__ void zero_slots_after_copy(const ScoreParams &p, unsigned char *lds, int buf) {
   if ((threadIdx.x & 63) != 0) return;
   const int wave = threadIdx.x >> 6;
-  if (wave == p.lo_owner) Elem<PT>::zero(buffer_consts<PT>(p, lds, buf).lo);
-  if (wave == p.hi_owner) Elem<PT>::zero(buffer_consts<PT>(p, lds, buf).hi);
+  if (wave == p.lo_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).lo);
+  if (wave == p.hi_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).hi);
 }
 
 __device__ __forceinline__ void init_lds(const ScoreParams &p, unsigned char *lds) {
@@ -164,12 +167,12 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
       double y = f0t;
 #pragma unroll
       for (int k = 0; k < K; ++k) y = __builtin_fma(c[s][k], ut[k], y);
-      if constexpr (WILD) y = (__builtin_fabs(y) < kWildLimit) ? y : -2.0 * Elem<PT>::bytes;
+      if constexpr (WILD) y = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
       addr[s] = clamp_i32(low_word(y + magic), lo, hi);
     }
     float v[TPL];
 #pragma unroll
-    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(addr[s]);
+    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(Elem<PT>::bytes * addr[s]);
 #pragma unroll
     for (int s = 0; s < TPL; ++s) acc[s] += v[s];
     if ((a & 7) == 7 || a + 1 == p.n_seg) {
@@ -272,16 +275,15 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
 #pragma unroll
       for (int k = 0; k < EMRI_MAX_K; ++k)
         if (k < K) y = __builtin_fma(c[k], sc[1 + k], y);
-      const double x = y * (1.0 / E);          // exact: the position in bins
-      if (__builtin_fabs(x) <= 1.7976931348623157e308 && live) {
-        const double fr = x - __builtin_floor(x);
+      if (__builtin_fabs(y) <= 1.7976931348623157e308 && live) {
+        const double fr = y - __builtin_floor(y);
         if (__builtin_fabs(fr - 0.5) < kNearTie) ++near;
       }
-      const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0 * E;
+      const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
       const BufConst &bc = buf ? bc1 : bc0;
       const int word = low_word(ys + bc.magic);
-      const int b = (word - (lds_address(lds) + buf * p.buf_bytes + kLeadIn)) / E;
-      acc += Elem<PT>::load(clamp_i32(word, bc.lo, bc.hi));
+      const int b = word - bc.base;
+      acc += Elem<PT>::load(E * clamp_i32(word, bc.lo, bc.hi));
       if (live && p.bins) p.bins[(size_t)j * p.n_seg + a] = (b >= p.k_min && b <= p.k_max) ? b : -1;
       if ((a & 7) == 7 || a + 1 == p.n_seg) {
         sum += (double)acc;
@@ -296,9 +298,9 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
   if (p.near_tie && near) atomicAdd(p.near_tie, near);
 }
 
-// Per-segment constants E*f0*T, E*U*T (FP64; E = power element bytes) and the
-// bounds of the wild-template test: bound[0] = max |E f0 T|,
-// bound[1+k] = max_alpha |E U[alpha,k] T| (+inf if an entry is not finite).
+// Per-segment constants f0*T, U*T (FP64) and the bounds of the wild-template
+// test: bound[0] = max |f0 T|, bound[1+k] = max_alpha |U[alpha,k] T| (+inf if
+// an entry is not finite).  `scale` multiplies every constant (1 here).
 // Also clears the near-tie counter.
 __global__ __launch_bounds__(256) void score_prep_kernel(const double *__restrict__ f0, const double *__restrict__ U,
                                                          int K, int n_seg, double t_sft, double scale, double *seg,

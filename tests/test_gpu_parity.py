@@ -36,8 +36,10 @@ def score_gpu(emri, P, f0, U, C, t_sft, top_k, dtype="f32", **kw):
     import torch
     spec = emri.spectrogram_from_power(np.asarray(P), t_sft, dtype)
     K = U.shape[1]
+    C = np.asarray(C, dtype=np.float32)
+    assert C.ndim == 2 and C.shape[1] == K
     res = emri.score_tracks(spec, _t(f0, torch.float64), _t(np.asarray(U).reshape(len(f0), K), torch.float64),
-                            _t(np.asarray(C, dtype=np.float32).reshape(-1, K)), top_k, **kw)
+                            _t(C), top_k, **kw)
     torch.cuda.synchronize()
     return {k: _np(v) for k, v in res.items()}
 
