@@ -101,15 +101,17 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
 
   // LDS staging geometry: a 16-byte lead-in, the row of n_bins elements rounded
-  // up to 16 bytes and copied in 1 KB wave chunks, and a 16-byte tail; two
-  // buffers.  The slots just below k_min and above k_max hold zeros.
+  // up to 16 bytes and copied in 1 KB wave chunks, and a 16-byte tail; two to
+  // four buffers.  The slots just below k_min and above k_max hold zeros.
   const int eb = elem_bytes(power->dtype);
   const int copy_bytes = (int)round_up((size_t)power->n_bins * eb, 16);
   const int row_chunks = (copy_bytes + 1023) / 1024;
   const int buf_bytes = SCORE_LDS_LEAD + row_chunks * 1024 + 16;
-  const size_t lds = 2 * (size_t)buf_bytes;
-  if (lds > kLdsLimit)
+  // two halves of one or two row buffers
+  int nbuf = (int)(kLdsLimit / (size_t)buf_bytes) >= 4 ? 4 : 2;
+  if ((size_t)nbuf * buf_bytes > kLdsLimit)
     return fail(EMRI_EUNSUPPORTED, "a spectrogram row of %d bins does not fit twice in LDS", power->n_bins);
+  const size_t lds = (size_t)nbuf * buf_bytes;
   auto owner = [&](int bin) {       // wave whose copy writes bin `bin`, or -1
     if (bin < 0) return -1;
     const int chunk = bin * eb / 1024;
@@ -149,6 +151,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     p.copy_bytes = copy_bytes;
     p.row_chunks = row_chunks;
     p.buf_bytes = buf_bytes;
+    p.nbuf = nbuf;
     p.lo_owner = owner(k_min - 1);
     p.hi_owner = owner(k_max + 1);
     const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;

@@ -7,10 +7,10 @@
 //     contiguous range of templates and walks it in tiles of TPL*512 templates:
 //     lane l holds TPL templates (j = tile + s*512 + l), their K coefficients
 //     widened to FP64 and kept in VGPRs for the whole tile.
-//   * For each segment alpha the power row P[alpha, 0..n_bins) is staged in LDS
-//     by asynchronous global->LDS copies (global_load_lds_dwordx4, 1 KB per wave
-//     instruction) into one of two buffers, so the copy of row alpha+1 overlaps
-//     the gathers from row alpha.  Every workgroup walks the rows in the same
+//   * Each power row P[alpha, 0..n_bins) is staged in LDS by asynchronous
+//     global->LDS copies (global_load_lds_dwordx4, 1 KB per wave instruction).
+//     Two halves of G = 1 or 2 row buffers alternate: while the G rows of one
+//     step are gathered from, the next G rows are copied into the other half.  Every workgroup walks the rows in the same
 //     order, so the 32 CUs of an XCD share each row in their L2.
 //   * Per (template, segment), with E = element size in bytes and B = the LDS
 //     byte address of bin 0 of the current buffer:
@@ -99,92 +99,170 @@ __device__ __forceinline__ BufConst buffer_consts(const ScoreParams &p, const un
 
 __device__ __forceinline__ int low_word(double y) { return (int)(unsigned)__double2loint(y); }
 
+// Wave index as a wave-uniform (scalar) value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Rows are staged in LDS through 2G buffers (G = p.nbuf / 2 rows per step):
+// during step s the rows [sG, sG+G) are read from buffer half s & 1 while the
+// copies of the next G rows fill the other half; a step ends by waiting for
+// its copies and a workgroup barrier.  Wave w copies the 1 KB chunks w, w+8,
+// w+16, ... of every row.  A lane's source offset inside a row is the same for
+// every row, so it is computed once: off0 for every chunk but the wave's last,
+// off_last (clamped to the row's end) for the last one.
+struct RowPipe {
+  int G;         // rows per step
+  int per_row;   // copies this wave issues per row
+  int off0;      // lane's byte offset of its 16 bytes in chunk `wave`
+  int off_last;  // same for this wave's last chunk, relative to that chunk's start offset
+};
+
 // Issue the asynchronous copy of power row `alpha` into LDS buffer `buf`.
 // Every lane copies 16 bytes; lanes past the row re-read its last 16 bytes and
 // write them past the row's end inside the buffer, where no gather looks.
-__device__ __forceinline__ void issue_row_copy(const ScoreParams &p, int alpha, unsigned char *lds, int buf) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const char *src = reinterpret_cast<const char *>(p.power) + (size_t)alpha * (size_t)p.row_bytes_pitch;
-  unsigned char *dst = lds + buf * p.buf_bytes + kLeadIn;
-  for (int c = wave; c < p.row_chunks; c += SCORE_THREADS / 64) {
-    int off = (c * 64 + lane) * 16;
-    off = off < p.copy_bytes ? off : p.copy_bytes - 16;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + off),
-                                     (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
+__device__ __forceinline__ void issue_row_copy(const ScoreParams &p, const RowPipe &rp, int alpha,
+                                               unsigned char *lds, int buf) {
+  const int wave = wave_id();
+  const char *row = reinterpret_cast<const char *>(p.power) + (size_t)alpha * (size_t)p.row_bytes_pitch;
+  unsigned char *dst = lds + buf * p.buf_bytes + kLeadIn + wave * 1024;
+  for (int i = 0; i < rp.per_row; ++i) {
+    const unsigned voff = (unsigned)(i + 1 < rp.per_row ? rp.off0 : rp.off_last);
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(row + (size_t)i * 8192 + voff),
+                                     (__attribute__((address_space(3))) void *)(dst + i * 8192), 16, 0, 0);
   }
 }
-
-__device__ __forceinline__ void wait_row_copies() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // Zero slots just outside [k_min, k_max].  A slot inside the copied part of a
 // row is rewritten after every copy by the wave whose copy covers it; a slot
 // outside it is written once at kernel start.
 template <typename PT>
 __device__ __forceinline__ void zero_slots_after_copy(const ScoreParams &p, unsigned char *lds, int buf) {
+  const int wave = wave_id();
   if ((threadIdx.x & 63) != 0) return;
-  const int wave = threadIdx.x >> 6;
   if (wave == p.lo_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).lo);
   if (wave == p.hi_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).hi);
 }
 
+__device__ __forceinline__ RowPipe pipe_init(const ScoreParams &p) {
+  RowPipe rp;
+  rp.G = p.nbuf >> 1;
+  const int wave = wave_id();
+  rp.per_row = wave < p.row_chunks ? (p.row_chunks - wave + SCORE_THREADS / 64 - 1) / (SCORE_THREADS / 64) : 0;
+  rp.off0 = (wave * 64 + (int)(threadIdx.x & 63)) * 16;
+  const int last_start = (rp.per_row > 0 ? rp.per_row - 1 : 0) * 8192;
+  const int last_off = rp.off0 + last_start;
+  rp.off_last = (last_off < p.copy_bytes ? last_off : p.copy_bytes - 16) - last_start;
+  return rp;
+}
+
+// Queue the copies of rows [first, first + G) into buffer half `half`.
+__device__ __forceinline__ void pipe_issue(const ScoreParams &p, const RowPipe &rp, unsigned char *lds, int first,
+                                           int half) {
+  for (int i = 0; i < rp.G; ++i)
+    if (first + i < p.n_seg) issue_row_copy(p, rp, first + i, lds, half * rp.G + i);
+}
+
+// Wait for this wave's copies, re-zero the range slots of half `half`, and
+// publish the rows to the workgroup.
+template <typename PT>
+__device__ __forceinline__ void pipe_publish(const ScoreParams &p, const RowPipe &rp, unsigned char *lds, int half) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  for (int i = 0; i < rp.G; ++i) zero_slots_after_copy<PT>(p, lds, half * rp.G + i);
+  __syncthreads();
+}
+
 __device__ __forceinline__ void init_lds(const ScoreParams &p, unsigned char *lds) {
-  // lead-in and tail of both buffers
-  for (int b = 0; b < 2; ++b) {
+  // lead-in and tail of every buffer
+  for (int b = 0; b < p.nbuf; ++b) {
     unsigned char *buf = lds + b * p.buf_bytes;
     for (int i = threadIdx.x; i < kLeadIn; i += SCORE_THREADS) buf[i] = 0;
     for (int i = kLeadIn + p.row_chunks * 1024 + threadIdx.x; i < p.buf_bytes; i += SCORE_THREADS) buf[i] = 0;
   }
 }
 
-// One tile of TPL slots of 512 templates against every segment.
+template <int K>
+__device__ __forceinline__ void load_segment(const ScoreParams &p, int a, double &f0t, double (&ut)[K > 0 ? K : 1]) {
+  const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
+  f0t = sc[0];
+#pragma unroll
+  for (int k = 0; k < K; ++k) ut[k] = sc[1 + k];
+}
+
+// LDS element addresses of the TPL templates' bins in one segment.  k-outer
+// order keeps TPL independent FMA chains in flight (FP64 FMA latency is longer
+// than its issue time).
+template <int K, int TPL, bool WILD>
+__device__ __forceinline__ void bin_addresses(const double (&c)[TPL][K > 0 ? K : 1], double f0t,
+                                              const double (&ut)[K > 0 ? K : 1], const BufConst &bc,
+                                              int (&addr)[TPL]) {
+  double y[TPL];
+#pragma unroll
+  for (int s = 0; s < TPL; ++s) y[s] = f0t;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) y[s] = __builtin_fma(c[s][k], ut[k], y[s]);
+  }
+#pragma unroll
+  for (int s = 0; s < TPL; ++s) {
+    double ys = y[s];
+    if constexpr (WILD) ys = (__builtin_fabs(ys) < kWildLimit) ? ys : -2.0;
+    addr[s] = clamp_i32(low_word(ys + bc.magic), bc.lo, bc.hi);
+  }
+}
+
+// One tile of TPL slots of 512 templates against every segment.  Software
+// pipelined per wave: the gathers of segment r are in flight while the bins of
+// segment r+1 are computed (its constants were loaded one segment earlier).
 template <int K, int TPL, typename PT, bool WILD>
 __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *lds,
                                          const double (&c)[TPL][K > 0 ? K : 1], double (&sum)[TPL]) {
+  constexpr int E = Elem<PT>::bytes;
   float acc[TPL];
 #pragma unroll
   for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
-  const BufConst bc0 = buffer_consts<PT>(p, lds, 0), bc1 = buffer_consts<PT>(p, lds, 1);
-  if (p.n_seg > 0) issue_row_copy(p, 0, lds, 0);
-  wait_row_copies();
-  zero_slots_after_copy<PT>(p, lds, 0);
-  __syncthreads();
-  for (int a = 0; a < p.n_seg; ++a) {
-    const int buf = a & 1;
-    if (a + 1 < p.n_seg) issue_row_copy(p, a + 1, lds, buf ^ 1);
-    const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
-    const double f0t = sc[0];
-    double ut[K > 0 ? K : 1];
+  const RowPipe rp = pipe_init(p);
+  pipe_issue(p, rp, lds, 0, 0);
+  pipe_publish<PT>(p, rp, lds, 0);
+  int addr[TPL];
+  double f0t, ut[K > 0 ? K : 1];
+  if (p.n_seg > 0) {
+    load_segment<K>(p, 0, f0t, ut);
+    bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, 0), addr);
+    load_segment<K>(p, p.n_seg > 1 ? 1 : 0, f0t, ut);
+  }
+  __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0): nothing scalar in flight entering the loop
+  int half = 0;
+  for (int r0 = 0; r0 < p.n_seg; r0 += rp.G) {
+    pipe_issue(p, rp, lds, r0 + rp.G, half ^ 1);
+    for (int i = 0; i < rp.G; ++i) {
+      const int r = r0 + i;
+      if (r >= p.n_seg) break;
+      float v[TPL];
 #pragma unroll
-    for (int k = 0; k < K; ++k) ut[k] = sc[1 + k];
-    const double magic = buf ? bc1.magic : bc0.magic;
-    const int lo = buf ? bc1.lo : bc0.lo, hi = buf ? bc1.hi : bc0.hi;
-    // All TPL slots are evaluated even in a partial last tile (their lanes hold
-    // zero coefficients and read in-bounds LDS).  Addresses first, then all
-    // gathers, then the sums, so the gathers of one segment overlap.
-    int addr[TPL];
+      for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(E * addr[s]);
+      // Bins of segment r+1 (for the last segment this computes clamped, unused
+      // addresses), then the constants of segment r+2, issued after the FMAs so
+      // that the wait for this segment's gathers also covers them.
+      const int nb = i + 1 < rp.G ? half * rp.G + i + 1 : (half ^ 1) * rp.G;
+      bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, nb), addr);
+      __builtin_amdgcn_sched_barrier(0);
+      load_segment<K>(p, r + 2 < p.n_seg ? r + 2 : p.n_seg - 1, f0t, ut);
+      // lgkmcnt(0): this segment's gathers and the scalar loads just issued;
+      // the next segment's FMAs then start without waiting for its own gathers.
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < TPL; ++s) {
-      double y = f0t;
+      for (int s = 0; s < TPL; ++s) acc[s] += v[s];
+      if ((r & 7) == 7 || r + 1 == p.n_seg) {
 #pragma unroll
-      for (int k = 0; k < K; ++k) y = __builtin_fma(c[s][k], ut[k], y);
-      if constexpr (WILD) y = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
-      addr[s] = clamp_i32(low_word(y + magic), lo, hi);
-    }
-    float v[TPL];
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(Elem<PT>::bytes * addr[s]);
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) acc[s] += v[s];
-    if ((a & 7) == 7 || a + 1 == p.n_seg) {
-#pragma unroll
-      for (int s = 0; s < TPL; ++s) {
-        sum[s] += (double)acc[s];
-        acc[s] = 0.0f;
+        for (int s = 0; s < TPL; ++s) {
+          sum[s] += (double)acc[s];
+          acc[s] = 0.0f;
+        }
       }
     }
-    wait_row_copies();
-    if (a + 1 < p.n_seg) zero_slots_after_copy<PT>(p, lds, buf ^ 1);
-    __syncthreads();
+    pipe_publish<PT>(p, rp, lds, half ^ 1);
+    half ^= 1;
   }
 }
 
@@ -253,7 +331,6 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
   init_lds(p, lds);
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
-  const BufConst bc0 = buffer_consts<PT>(p, lds, 0), bc1 = buffer_consts<PT>(p, lds, 1);
   unsigned long long near = 0;
   for (int64_t t0 = j_begin; t0 < j_end; t0 += SCORE_THREADS) {
     const int64_t j = t0 + tid;
@@ -263,35 +340,36 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
     for (int k = 0; k < EMRI_MAX_K; ++k) c[k] = (k < K && live) ? (double)p.coeffs[(size_t)j * K + k] : 0.0;
     double sum = 0.0;
     float acc = 0.0f;
-    if (p.n_seg > 0) issue_row_copy(p, 0, lds, 0);
-    wait_row_copies();
-    zero_slots_after_copy<PT>(p, lds, 0);
-    __syncthreads();
-    for (int a = 0; a < p.n_seg; ++a) {
-      const int buf = a & 1;
-      if (a + 1 < p.n_seg) issue_row_copy(p, a + 1, lds, buf ^ 1);
-      const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
-      double y = sc[0];
+    const RowPipe rp = pipe_init(p);
+    pipe_issue(p, rp, lds, 0, 0);
+    pipe_publish<PT>(p, rp, lds, 0);
+    int half = 0;
+    for (int r0 = 0; r0 < p.n_seg; r0 += rp.G) {
+      pipe_issue(p, rp, lds, r0 + rp.G, half ^ 1);
+      for (int i = 0; i < rp.G && r0 + i < p.n_seg; ++i) {
+        const int a = r0 + i;
+        const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
+        double y = sc[0];
 #pragma unroll
-      for (int k = 0; k < EMRI_MAX_K; ++k)
-        if (k < K) y = __builtin_fma(c[k], sc[1 + k], y);
-      if (__builtin_fabs(y) <= 1.7976931348623157e308 && live) {
-        const double fr = y - __builtin_floor(y);
-        if (__builtin_fabs(fr - 0.5) < kNearTie) ++near;
+        for (int k = 0; k < EMRI_MAX_K; ++k)
+          if (k < K) y = __builtin_fma(c[k], sc[1 + k], y);
+        if (__builtin_fabs(y) <= 1.7976931348623157e308 && live) {
+          const double fr = y - __builtin_floor(y);
+          if (__builtin_fabs(fr - 0.5) < kNearTie) ++near;
+        }
+        const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
+        const BufConst bc = buffer_consts<PT>(p, lds, half * rp.G + i);
+        const int word = low_word(ys + bc.magic);
+        const int b = word - bc.base;
+        acc += Elem<PT>::load(E * clamp_i32(word, bc.lo, bc.hi));
+        if (live && p.bins) p.bins[(size_t)j * p.n_seg + a] = (b >= p.k_min && b <= p.k_max) ? b : -1;
+        if ((a & 7) == 7 || a + 1 == p.n_seg) {
+          sum += (double)acc;
+          acc = 0.0f;
+        }
       }
-      const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
-      const BufConst &bc = buf ? bc1 : bc0;
-      const int word = low_word(ys + bc.magic);
-      const int b = word - bc.base;
-      acc += Elem<PT>::load(E * clamp_i32(word, bc.lo, bc.hi));
-      if (live && p.bins) p.bins[(size_t)j * p.n_seg + a] = (b >= p.k_min && b <= p.k_max) ? b : -1;
-      if ((a & 7) == 7 || a + 1 == p.n_seg) {
-        sum += (double)acc;
-        acc = 0.0f;
-      }
-      wait_row_copies();
-      if (a + 1 < p.n_seg) zero_slots_after_copy<PT>(p, lds, buf ^ 1);
-      __syncthreads();
+      pipe_publish<PT>(p, rp, lds, half ^ 1);
+      half ^= 1;
     }
     if (live && p.stat) p.stat[j] = (float)sum;
   }
