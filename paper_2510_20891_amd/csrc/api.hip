@@ -107,8 +107,9 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   const int copy_bytes = (int)round_up((size_t)power->n_bins * eb, 16);
   const int row_chunks = (copy_bytes + 1023) / 1024;
   const int buf_bytes = SCORE_LDS_LEAD + row_chunks * 1024 + 16;
-  // two halves of one or two row buffers
-  int nbuf = (int)(kLdsLimit / (size_t)buf_bytes) >= 4 ? 4 : 2;
+  // two halves of G = 1, 2 or 4 row buffers, as many as fit
+  const int fit = (int)(kLdsLimit / (size_t)buf_bytes);
+  const int nbuf = fit >= 8 ? 8 : (fit >= 4 ? 4 : 2);
   if ((size_t)nbuf * buf_bytes > kLdsLimit)
     return fail(EMRI_EUNSUPPORTED, "a spectrogram row of %d bins does not fit twice in LDS", power->n_bins);
   const size_t lds = (size_t)nbuf * buf_bytes;

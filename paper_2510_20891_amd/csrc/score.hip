@@ -9,7 +9,7 @@
 //     widened to FP64 and kept in VGPRs for the whole tile.
 //   * Each power row P[alpha, 0..n_bins) is staged in LDS by asynchronous
 //     global->LDS copies (global_load_lds_dwordx4, 1 KB per wave instruction).
-//     Two halves of G = 1 or 2 row buffers alternate: while the G rows of one
+//     Two halves of G = 1, 2 or 4 row buffers alternate: while the G rows of one
 //     step are gathered from, the next G rows are copied into the other half.  Every workgroup walks the rows in the same
 //     order, so the 32 CUs of an XCD share each row in their L2.
 //   * Per (template, segment), with E = element size in bytes and B = the LDS

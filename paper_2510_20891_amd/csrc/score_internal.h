@@ -30,7 +30,7 @@ struct ScoreParams {
   int copy_bytes;             // bytes of a row copied to LDS (n_bins elements, 16-byte multiple)
   int row_chunks;             // 1 KB wave copies per row
   int buf_bytes;              // bytes per LDS row buffer (multiple of 16)
-  int nbuf;                   // LDS row buffers: 2 or 4 (two halves of G = nbuf/2 rows)
+  int nbuf;                   // LDS row buffers: 2, 4 or 8 (two halves of G = nbuf/2 rows)
   int lo_owner, hi_owner;     // wave that re-zeroes the slot below / above the bin range after a copy (-1: none)
 };
 
