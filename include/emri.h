@@ -163,6 +163,62 @@ int score_tracks(const emri_power *power, const double *f0, const double *U, int
                  int32_t *bins, int64_t *n_near_tie, const score_opts *opts,
                  void *workspace, size_t workspace_bytes, void *hip_stream);
 
+/*
+ * Batched form: many scoring problems in one persistent launch.
+ *
+ * A problem is one batch of coefficient vectors scored against one
+ * spectrogram exactly as score_tracks does (several problems may share a
+ * spectrogram, e.g. many requests against a few resident data streams).  All
+ * problems of a batch share K and the power storage type; their spectrogram
+ * shapes, segment counts, template counts, bin ranges and top_k may differ.
+ * Each template's statistic is summed in the same order as in score_tracks, so
+ * every result is bit-for-bit the one a standalone score_tracks call gives.
+ *
+ * score_batched_plan validates the problems, splits their tiles of templates
+ * into one contiguous share of near-equal work per workgroup (one workgroup
+ * per compute unit), and writes the launch tables into the workspace with
+ * asynchronous host-to-device copies on hip_stream (the host arrays are
+ * consumed before the call returns).  score_batched_run only launches kernels
+ * that read those tables, so it may be captured into a HIP graph and replayed;
+ * a replay re-reads the problems' current device inputs.  The plan stays valid
+ * while the workspace and every problem buffer stay allocated.
+ */
+typedef struct {
+  emri_power power;          /* spectrogram of this problem                        */
+  const double *f0;          /* device FP64[n_seg]                                  */
+  const double *U;           /* device FP64[n_seg * K]                              */
+  const float *coeffs;       /* device FP32[n_tmpl * K]                             */
+  int64_t n_tmpl;            /* 0 .. 2^31 - 1                                       */
+  int32_t top_k;             /* 0 .. 4096                                           */
+  int32_t k_min, k_max;      /* bin range; k_max < 0 means n_bins - 1               */
+  int32_t reserved;          /* must be zero                                        */
+  float *stat;               /* device FP32[n_tmpl], or NULL (kept in the workspace)*/
+  float *topk_val;           /* device FP32[top_k] (may be NULL if top_k == 0)      */
+  int64_t *topk_idx;         /* device INT64[top_k]                                 */
+} emri_problem;
+
+typedef struct {
+  int32_t rows_per_step;       /* spectrogram rows staged per step: 0 = as many as fit, or 1, 2, 4 */
+  int32_t templates_per_lane;  /* 0 = default; otherwise a value score_batched_tile_options lists  */
+  int32_t reserved[6];         /* must be zero                                                     */
+} batch_opts;
+
+typedef struct {
+  int64_t opaque[24];          /* filled by score_batched_plan; caller-owned, not interpreted */
+} emri_batch_plan;
+
+/* Bytes of workspace a batch needs (256-byte aligned workspace required). */
+int score_batched_workspace_size(const emri_problem *problems, int32_t n_problems, int32_t K, size_t *bytes);
+
+/* Templates-per-lane values compiled for K (written to out[0..*n_out)); the
+ * first is the default.  Used by autotuners. */
+int score_batched_tile_options(int32_t K, int32_t *out, int32_t *n_out);
+
+int score_batched_plan(const emri_problem *problems, int32_t n_problems, int32_t K, const batch_opts *opts,
+                       void *workspace, size_t workspace_bytes, emri_batch_plan *plan, void *hip_stream);
+
+int score_batched_run(const emri_batch_plan *plan, void *hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *emri_status_string(int status);
 

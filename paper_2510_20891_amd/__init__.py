@@ -47,6 +47,20 @@ class _Opts(ctypes.Structure):
 
 _vp, _i32, _i64, _dbl, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
 
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("power", _Power), ("f0", _vp), ("U", _vp), ("coeffs", _vp), ("n_tmpl", _i64),
+                ("top_k", _i32), ("k_min", _i32), ("k_max", _i32), ("reserved", _i32),
+                ("stat", _vp), ("topk_val", _vp), ("topk_idx", _vp)]
+
+
+class _BatchOpts(ctypes.Structure):
+    _fields_ = [("rows_per_step", _i32), ("templates_per_lane", _i32), ("reserved", _i32 * 6)]
+
+
+class _Plan(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_int64 * 24)]
+
 SIGNATURES = {
     "build_sfts": (ctypes.c_int, [_vp, _i64, _dbl, _i32, _vp, ctypes.POINTER(_Power), _vp]),
     "build_basis": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -54,6 +68,11 @@ SIGNATURES = {
                                                    ctypes.POINTER(_sz)]),
     "score_tracks": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp,
                                     _vp, _vp, ctypes.POINTER(_Opts), _vp, _sz, _vp]),
+    "score_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_sz)]),
+    "score_batched_tile_options": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "score_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp,
+                                          _sz, ctypes.POINTER(_Plan), _vp]),
+    "score_batched_run": (ctypes.c_int, [ctypes.POINTER(_Plan), _vp]),
     "emri_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "emri_last_error": (ctypes.c_char_p, []),
 }
@@ -250,5 +269,83 @@ def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: boo
     return res
 
 
-__all__ = ["load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+@dataclass
+class Problem:
+    """One scoring problem of a batched launch (device tensors; outputs allocated if None)."""
+    spec: Spectrogram
+    f0: "object"
+    U: "object"
+    coeffs: "object"
+    top_k: int = 0
+    k_min: int = 0
+    k_max: int = -1
+    stat: "object" = None
+    topk_val: "object" = None
+    topk_idx: "object" = None
+
+
+def batched_tile_options(K: int) -> list[int]:
+    out = (ctypes.c_int32 * 4)()
+    n = ctypes.c_int32(0)
+    _check("score_batched_tile_options", load().score_batched_tile_options(int(K), out, ctypes.byref(n)))
+    return [int(out[i]) for i in range(n.value)]
+
+
+class BatchPlan:
+    """A planned batched launch over many problems (the batched form of score_tracks).
+
+    ``run()`` only launches kernels, so it can be captured in a HIP graph
+    (``torch.cuda.CUDAGraph``) and replayed; a replay re-reads the problems'
+    current device inputs.  Keep the plan (and its tensors) alive while it is used.
+    """
+
+    def __init__(self, problems: list, K: int, rows_per_step: int = 0, templates_per_lane: int = 0,
+                 workspace=None, stream=None):
+        import torch
+        self.problems = list(problems)
+        self.K = int(K)
+        arr = (_Problem * max(1, len(self.problems)))()
+        for i, pb in enumerate(self.problems):
+            _require_cuda(pb.f0, torch.float64, "f0")
+            _require_cuda(pb.U, torch.float64, "U")
+            _require_cuda(pb.coeffs, torch.float32, "coeffs")
+            dev = pb.coeffs.device
+            n = int(pb.coeffs.shape[0])
+            if pb.stat is None:
+                pb.stat = torch.empty(n, dtype=torch.float32, device=dev)
+            if pb.topk_val is None:
+                pb.topk_val = torch.empty(pb.top_k, dtype=torch.float32, device=dev)
+            if pb.topk_idx is None:
+                pb.topk_idx = torch.empty(pb.top_k, dtype=torch.int64, device=dev)
+            a = arr[i]
+            a.power = pb.spec._struct()
+            a.f0 = _ptr(pb.f0)
+            a.U = _ptr(pb.U) if self.K else None
+            a.coeffs = _ptr(pb.coeffs) if self.K and n else None
+            a.n_tmpl = n
+            a.top_k = int(pb.top_k)
+            a.k_min = int(pb.k_min)
+            a.k_max = int(pb.k_max)
+            a.stat = _ptr(pb.stat) if n else None
+            a.topk_val = _ptr(pb.topk_val) if pb.top_k else None
+            a.topk_idx = _ptr(pb.topk_idx) if pb.top_k else None
+        self._arr = arr
+        lib = load()
+        nbytes = ctypes.c_size_t(0)
+        _check("score_batched_workspace_size",
+               lib.score_batched_workspace_size(arr, len(self.problems), self.K, ctypes.byref(nbytes)))
+        dev = self.problems[0].coeffs.device if self.problems else torch.device("cuda")
+        self._ws = workspace or Workspace()
+        ws_ptr, ws_len = self._ws.get(int(nbytes.value), dev)
+        self.opts = _BatchOpts(int(rows_per_step), int(templates_per_lane))
+        self._plan = _Plan()
+        _check("score_batched_plan", lib.score_batched_plan(arr, len(self.problems), self.K, ctypes.byref(self.opts),
+                                                            ws_ptr, ws_len, ctypes.byref(self._plan),
+                                                            _stream(stream)))
+
+    def run(self, stream=None) -> None:
+        _check("score_batched_run", load().score_batched_run(ctypes.byref(self._plan), _stream(stream)))
+
+
+__all__ = ["Problem", "BatchPlan", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
            "Spectrogram", "spectrogram_from_power", "Workspace", "EmriError", "F32", "F16", "LIB_PATH"]

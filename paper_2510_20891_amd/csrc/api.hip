@@ -130,8 +130,17 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
 
   hipError_t err = hipSuccess;
   if (power->n_seg > 0 || validate) {
-    err = launch_score_prep(f0, U, K, power->n_seg, power->t_sft, 1.0, seg, L.seg_stride, bound,
-                            reinterpret_cast<unsigned long long *>(n_near_tie), stream);
+    PrepJob job{};
+    job.f0 = f0;
+    job.U = U;
+    job.seg = seg;
+    job.bound = bound;
+    job.near_tie = reinterpret_cast<unsigned long long *>(n_near_tie);
+    job.t_sft = power->t_sft;
+    job.K = K;
+    job.n_seg = power->n_seg;
+    job.seg_stride = L.seg_stride;
+    err = launch_score_prep(job, stream);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score prep launch: %s", hipGetErrorString(err));
   }
   if (n_tmpl > 0) {

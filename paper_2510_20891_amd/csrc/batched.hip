@@ -1,0 +1,353 @@
+// C ABI of the batched form: plan many scoring problems into one persistent
+// launch (work split by tiles of templates, weighted by segment count), then
+// run it with kernels that only read device tables, so the run can be captured
+// into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "score_internal.h"
+
+using namespace emri;
+
+namespace {
+
+constexpr size_t kLdsLimit = 163840;
+constexpr uint32_t kPlanMagic = 0x454d5242u;   // "EMRB"
+
+// What score_batched_run needs, stored inside the caller's emri_batch_plan.
+struct PlanData {
+  uint32_t magic;
+  int32_t n_problems;
+  int32_t n_topk;
+  int32_t cus;
+  int64_t max_topk_n;
+  BatchLaunch launch;
+  const PrepJob *prep_jobs;
+  const TopkJob *topk_jobs;
+  int32_t n_items;
+  int32_t has_work;
+};
+static_assert(sizeof(PlanData) <= sizeof(emri_batch_plan), "plan does not fit");
+
+int elem_bytes(int dtype) { return dtype == EMRI_F16 ? 2 : 4; }
+
+struct Geometry {
+  int copy_bytes, row_chunks, buf_bytes;
+};
+
+Geometry geometry(const emri_power &pw) {
+  Geometry g;
+  const int eb = elem_bytes(pw.dtype);
+  g.copy_bytes = (int)round_up((size_t)pw.n_bins * eb, 16);
+  g.row_chunks = (g.copy_bytes + 1023) / 1024;
+  g.buf_bytes = SCORE_LDS_LEAD + g.row_chunks * 1024 + 16;
+  return g;
+}
+
+int check_problem(const emri_problem &pb, int i, int K, int dtype) {
+  const emri_power &pw = pb.power;
+  if (pw.dtype != EMRI_F32 && pw.dtype != EMRI_F16) return fail(EMRI_EINVAL, "problem %d: unknown power dtype", i);
+  if (pw.dtype != dtype) return fail(EMRI_EINVAL, "problem %d: every problem must use the same power dtype", i);
+  if (pw.n_seg < 0 || pw.n_bins < 1) return fail(EMRI_EINVAL, "problem %d: n_seg < 0 or n_bins < 1", i);
+  if (pw.row_pitch < pw.n_bins || (pw.row_pitch % 8) != 0)
+    return fail(EMRI_EINVAL, "problem %d: row_pitch must be a multiple of 8 and >= n_bins", i);
+  if (!std::isfinite(pw.t_sft) || !(pw.t_sft > 0.0)) return fail(EMRI_EINVAL, "problem %d: bad t_sft", i);
+  if ((int64_t)pw.row_pitch * elem_bytes(pw.dtype) > INT32_MAX) return fail(EMRI_ERANGE, "problem %d: row too long", i);
+  if (pb.n_tmpl < 0 || pb.n_tmpl > INT32_MAX) return fail(EMRI_EINVAL, "problem %d: n_tmpl out of range", i);
+  if (pb.top_k < 0 || pb.top_k > EMRI_MAX_TOPK) return fail(EMRI_EINVAL, "problem %d: top_k out of range", i);
+  if (pb.reserved != 0) return fail(EMRI_EINVAL, "problem %d: reserved must be zero", i);
+  const int k_max = pb.k_max < 0 ? pw.n_bins - 1 : pb.k_max;
+  if (pb.k_min < 0 || k_max > pw.n_bins - 1 || pb.k_min > k_max)
+    return fail(EMRI_EINVAL, "problem %d: bin range outside the row", i);
+  if (pw.n_seg > 0 && !pw.data) return fail(EMRI_EINVAL, "problem %d: power data is NULL", i);
+  if (pw.n_seg > 0 && !pb.f0) return fail(EMRI_EINVAL, "problem %d: f0 is NULL", i);
+  if (pw.n_seg > 0 && K > 0 && !pb.U) return fail(EMRI_EINVAL, "problem %d: U is NULL", i);
+  if (pb.n_tmpl > 0 && K > 0 && !pb.coeffs) return fail(EMRI_EINVAL, "problem %d: coeffs is NULL", i);
+  if (pb.top_k > 0 && (!pb.topk_val || !pb.topk_idx)) return fail(EMRI_EINVAL, "problem %d: top-k outputs NULL", i);
+  const void *ptrs[] = {pw.data, pb.f0, pb.U, pb.coeffs, pb.stat, pb.topk_val, pb.topk_idx};
+  for (const void *p : ptrs)
+    if (p && !aligned16(p)) return fail(EMRI_EINVAL, "problem %d: device pointers must be 16-byte aligned", i);
+  return EMRI_OK;
+}
+
+// Workspace layout of a batch.
+struct Layout {
+  size_t params, prep, topk_jobs, items, block_items, seg, bound, stat, topk, total;
+  std::vector<size_t> seg_off, bound_off, stat_off, topk_off;
+};
+
+int seg_stride_of(int K) { return (K + 2) & ~1; }
+
+Layout make_layout(const emri_problem *pbs, int n, int K, int max_items, int grid) {
+  Layout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes > 0 ? bytes : 1, 256);
+    return at;
+  };
+  L.params = take(sizeof(ScoreParams) * n);
+  L.prep = take(sizeof(PrepJob) * n);
+  L.topk_jobs = take(sizeof(TopkJob) * n);
+  L.items = take(sizeof(BatchItem) * max_items);
+  L.block_items = take(sizeof(int) * (grid + 1));
+  L.seg = off;
+  for (int i = 0; i < n; ++i) {
+    const int ns = pbs[i].power.n_seg > 0 ? pbs[i].power.n_seg : 1;
+    L.seg_off.push_back(take(sizeof(double) * ns * seg_stride_of(K)));
+    L.bound_off.push_back(take(sizeof(double) * (EMRI_MAX_K + 1)));
+    L.stat_off.push_back(pbs[i].stat ? 0 : take(sizeof(float) * pbs[i].n_tmpl));
+    L.topk_off.push_back(pbs[i].top_k > 0 ? take(topk_workspace_bytes(pbs[i].top_k)) : 0);
+  }
+  L.total = off;
+  return L;
+}
+
+int tile_of(int K, int tpl_choice) { return tpl_choice * SCORE_THREADS; }
+
+int resolve_tpl(int K, int requested, int *tpl) {
+  const int def = score_templates_per_lane(K, false), alt = score_templates_per_lane(K, true);
+  if (requested == 0 || requested == def) {
+    *tpl = def;
+    return EMRI_OK;
+  }
+  if ((K == 8 || K == 16) && requested == alt) {
+    *tpl = alt;
+    return EMRI_OK;
+  }
+  return fail(EMRI_EUNSUPPORTED, "templates_per_lane %d is not compiled for K = %d", requested, K);
+}
+
+int max_items_for(const emri_problem *pbs, int n, int grid) { return n + grid; }
+
+}  // namespace
+
+extern "C" int score_batched_tile_options(int32_t K, int32_t *out, int32_t *n_out) {
+  clear_error();
+  if (!out || !n_out) return fail(EMRI_EINVAL, "out or n_out is NULL");
+  if (K < 0 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K outside [0, %d]", EMRI_MAX_K);
+  out[0] = score_templates_per_lane(K, false);
+  *n_out = 1;
+  if (K == 8 || K == 16) {
+    out[1] = score_templates_per_lane(K, true);
+    *n_out = 2;
+  }
+  return EMRI_OK;
+}
+
+static int batch_grid(int *grid) { return device_cu_count(grid); }
+
+extern "C" int score_batched_workspace_size(const emri_problem *problems, int32_t n_problems, int32_t K,
+                                            size_t *bytes) {
+  clear_error();
+  if (!bytes || (!problems && n_problems > 0)) return fail(EMRI_EINVAL, "NULL argument");
+  if (n_problems < 0 || n_problems > (1 << 20)) return fail(EMRI_EINVAL, "n_problems out of range");
+  if (K < 0 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K outside [0, %d]", EMRI_MAX_K);
+  const int dtype = n_problems > 0 ? problems[0].power.dtype : EMRI_F32;
+  for (int i = 0; i < n_problems; ++i) {
+    const int st = check_problem(problems[i], i, K, dtype);
+    if (st) return st;
+  }
+  // sized for the largest grid a gfx950 can have (256 compute units)
+  const int grid = 256;
+  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, grid), grid);
+  *bytes = L.total;
+  return EMRI_OK;
+}
+
+extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_problems, int32_t K, const batch_opts *opts,
+                                  void *workspace, size_t workspace_bytes, emri_batch_plan *plan, void *hip_stream) {
+  clear_error();
+  if (!plan || !workspace || (!problems && n_problems > 0)) return fail(EMRI_EINVAL, "NULL argument");
+  if (n_problems < 0 || n_problems > (1 << 20)) return fail(EMRI_EINVAL, "n_problems out of range");
+  if (K < 0 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K outside [0, %d]", EMRI_MAX_K);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
+  batch_opts o{};
+  if (opts) {
+    o = *opts;
+    for (int i = 0; i < 6; ++i)
+      if (o.reserved[i] != 0) return fail(EMRI_EINVAL, "batch_opts.reserved must be zero");
+  }
+  if (o.rows_per_step != 0 && o.rows_per_step != 1 && o.rows_per_step != 2 && o.rows_per_step != 4)
+    return fail(EMRI_EINVAL, "rows_per_step must be 0, 1, 2 or 4");
+  const int dtype = n_problems > 0 ? problems[0].power.dtype : EMRI_F32;
+  for (int i = 0; i < n_problems; ++i) {
+    const int st = check_problem(problems[i], i, K, dtype);
+    if (st) return st;
+  }
+  int tpl = 0, st = resolve_tpl(K, o.templates_per_lane, &tpl);
+  if (st) return st;
+
+  // staging geometry: the same number of rows per step for every problem,
+  // the most that fits the largest row (or the requested count)
+  int max_buf = SCORE_LDS_LEAD + 1024 + 16;
+  for (int i = 0; i < n_problems; ++i) max_buf = std::max(max_buf, geometry(problems[i].power).buf_bytes);
+  const int fit = (int)(kLdsLimit / (size_t)max_buf);
+  int G = fit >= 8 ? 4 : (fit >= 4 ? 2 : 1);
+  if (fit < 2) return fail(EMRI_EUNSUPPORTED, "a spectrogram row does not fit twice in LDS");
+  if (o.rows_per_step != 0) {
+    if (2 * o.rows_per_step > fit)
+      return fail(EMRI_EUNSUPPORTED, "rows_per_step %d does not fit in LDS for these rows", o.rows_per_step);
+    G = o.rows_per_step;
+  }
+  int cus = 0;
+  if ((st = batch_grid(&cus)) != EMRI_OK) return st;
+  const int grid = std::min(cus, 256);
+
+  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, grid), grid);
+  if (workspace_bytes < L.total)
+    return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
+  char *ws = reinterpret_cast<char *>(workspace);
+
+  // per-problem tables
+  std::vector<ScoreParams> params(n_problems);
+  std::vector<PrepJob> preps(n_problems);
+  std::vector<TopkJob> topks;
+  int64_t max_topk_n = 0;
+  for (int i = 0; i < n_problems; ++i) {
+    const emri_problem &pb = problems[i];
+    const Geometry g = geometry(pb.power);
+    const int eb = elem_bytes(pb.power.dtype);
+    const int k_max = pb.k_max < 0 ? pb.power.n_bins - 1 : pb.k_max;
+    auto owner = [&](int bin) {
+      if (bin < 0) return -1;
+      const int chunk = bin * eb / 1024;
+      return chunk < g.row_chunks ? chunk % (SCORE_THREADS / 64) : -1;
+    };
+    ScoreParams &p = params[i];
+    std::memset(&p, 0, sizeof p);
+    p.power = pb.power.data;
+    p.seg = reinterpret_cast<const double *>(ws + L.seg_off[i]);
+    p.bound = reinterpret_cast<const double *>(ws + L.bound_off[i]);
+    p.coeffs = pb.coeffs;
+    p.stat = pb.stat ? pb.stat : reinterpret_cast<float *>(ws + L.stat_off[i]);
+    p.n_tmpl = pb.n_tmpl;
+    p.n_seg = pb.power.n_seg;
+    p.seg_stride = seg_stride_of(K);
+    p.k_min = pb.k_min;
+    p.k_max = k_max;
+    p.row_bytes_pitch = pb.power.row_pitch * eb;
+    p.copy_bytes = g.copy_bytes;
+    p.row_chunks = g.row_chunks;
+    p.buf_bytes = g.buf_bytes;
+    p.nbuf = 2 * G;
+    p.lo_owner = owner(pb.k_min - 1);
+    p.hi_owner = owner(k_max + 1);
+    PrepJob &pj = preps[i];
+    std::memset(&pj, 0, sizeof pj);
+    pj.f0 = pb.f0;
+    pj.U = pb.U;
+    pj.seg = reinterpret_cast<double *>(ws + L.seg_off[i]);
+    pj.bound = reinterpret_cast<double *>(ws + L.bound_off[i]);
+    pj.t_sft = pb.power.t_sft;
+    pj.K = K;
+    pj.n_seg = pb.power.n_seg;
+    pj.seg_stride = seg_stride_of(K);
+    if (pb.top_k > 0) {
+      topks.push_back(make_topk_job(p.stat, pb.n_tmpl, pb.top_k, pb.topk_val, pb.topk_idx, ws + L.topk_off[i]));
+      max_topk_n = std::max(max_topk_n, pb.n_tmpl);
+    }
+  }
+
+  // work split: tiles of templates, each weighted by its problem's segments
+  // (plus one for the tile's fixed cost), cut into `grid` contiguous shares
+  const int64_t tile = tile_of(K, tpl);
+  std::vector<int64_t> tiles_of(n_problems);
+  double total = 0.0;
+  for (int i = 0; i < n_problems; ++i) {
+    tiles_of[i] = (problems[i].n_tmpl + tile - 1) / tile;
+    total += (double)tiles_of[i] * (problems[i].power.n_seg + 1);
+  }
+  std::vector<BatchItem> items;
+  std::vector<int> block_items(grid + 1, 0);
+  {
+    int block = 0;
+    double acc = 0.0;
+    const double share = total / grid;
+    for (int i = 0; i < n_problems; ++i) {
+      const double w = (double)(problems[i].power.n_seg + 1);
+      int64_t t = 0;
+      while (t < tiles_of[i]) {
+        // tiles of problem i that still fit in this block's share
+        const double room = (block + 1) * share - acc;
+        int64_t take = (block == grid - 1) ? tiles_of[i] - t : (int64_t)std::floor(room / w + 0.5);
+        if (take <= 0) {
+          if (block < grid - 1) {
+            block_items[++block] = (int)items.size();
+            continue;
+          }
+          take = tiles_of[i] - t;
+        }
+        take = std::min(take, tiles_of[i] - t);
+        BatchItem it{};
+        it.stream = i;
+        it.begin = t * tile;
+        it.end = std::min(problems[i].n_tmpl, (t + take) * tile);
+        items.push_back(it);
+        acc += (double)take * w;
+        t += take;
+      }
+    }
+    for (int b = block + 1; b <= grid; ++b) block_items[b] = (int)items.size();
+  }
+  if ((int)items.size() > max_items_for(problems, n_problems, grid))
+    return fail(EMRI_ERANGE, "work list longer than planned");
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t err = hipSuccess;
+  auto copy = [&](size_t off, const void *src, size_t bytes) {
+    if (bytes && err == hipSuccess) err = hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, stream);
+  };
+  copy(L.params, params.data(), sizeof(ScoreParams) * params.size());
+  copy(L.prep, preps.data(), sizeof(PrepJob) * preps.size());
+  copy(L.topk_jobs, topks.data(), sizeof(TopkJob) * topks.size());
+  copy(L.items, items.data(), sizeof(BatchItem) * items.size());
+  copy(L.block_items, block_items.data(), sizeof(int) * block_items.size());
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched plan copies: %s", hipGetErrorString(err));
+
+  PlanData pd{};
+  pd.magic = kPlanMagic;
+  pd.n_problems = n_problems;
+  pd.n_topk = (int)topks.size();
+  pd.cus = cus;
+  pd.max_topk_n = max_topk_n;
+  pd.launch.params = reinterpret_cast<const ScoreParams *>(ws + L.params);
+  pd.launch.items = reinterpret_cast<const BatchItem *>(ws + L.items);
+  pd.launch.block_items = reinterpret_cast<const int *>(ws + L.block_items);
+  pd.launch.grid = grid;
+  pd.launch.K = K;
+  pd.launch.dtype = dtype;
+  pd.launch.tpl = tpl;
+  pd.launch.lds = (size_t)(2 * G) * max_buf;
+  pd.prep_jobs = reinterpret_cast<const PrepJob *>(ws + L.prep);
+  pd.topk_jobs = reinterpret_cast<const TopkJob *>(ws + L.topk_jobs);
+  pd.n_items = (int)items.size();
+  pd.has_work = items.empty() ? 0 : 1;
+  std::memset(plan, 0, sizeof *plan);
+  std::memcpy(plan, &pd, sizeof pd);
+  return EMRI_OK;
+}
+
+extern "C" int score_batched_run(const emri_batch_plan *plan, void *hip_stream) {
+  clear_error();
+  if (!plan) return fail(EMRI_EINVAL, "plan is NULL");
+  PlanData pd;
+  std::memcpy(&pd, plan, sizeof pd);
+  if (pd.magic != kPlanMagic) return fail(EMRI_EINVAL, "plan was not made by score_batched_plan");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipError_t err = launch_score_prep_batched(pd.prep_jobs, pd.n_problems, stream);
+  if (err == hipSuccess && pd.has_work) err = launch_score_batched(pd.launch, stream);
+  if (err == hipSuccess && pd.n_topk > 0) {
+    TopkJobs J;
+    std::memset(&J, 0, sizeof J);
+    J.jobs = pd.topk_jobs;
+    err = launch_topk_jobs(J, pd.n_topk, pd.max_topk_n, pd.cus, stream);
+  }
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched launch: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}

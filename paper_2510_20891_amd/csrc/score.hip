@@ -266,13 +266,11 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   }
 }
 
+// Score templates [j_begin, j_end) of one stream (the workgroup's share).
 template <int K, int TPL, typename PT>
-__global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+__device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
+                                            int64_t j_end) {
   const int tid = threadIdx.x;
-  init_lds(p, lds);
-  const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
-  const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
   const_dptr bnd_src = (const_dptr)p.bound;
   double bound_u[K > 0 ? K : 1];
 #pragma unroll
@@ -317,6 +315,35 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p
       const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
       if (j < j_end) p.stat[j] = (float)sum[s];
     }
+  }
+}
+
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  init_lds(p, lds);
+  const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
+  const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
+  score_range<K, TPL, PT>(p, lds, j_begin, j_end);
+}
+
+// Batched form: one persistent launch over many streams.  Workgroup g walks
+// the work items [block_items[g], block_items[g+1]); an item is a range of
+// one stream's templates, and every stream carries its own spectrogram,
+// constants, bin range and staging geometry.
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_batched_kernel(const ScoreParams *__restrict__ params,
+                                                                      const BatchItem *__restrict__ items,
+                                                                      const int *__restrict__ block_items) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  typedef const __attribute__((address_space(4))) int *const_ints;
+  const int first = ((const_ints)block_items)[blockIdx.x];
+  const int last = ((const_ints)block_items)[blockIdx.x + 1];
+  for (int it = first; it < last; ++it) {
+    const BatchItem item = load_uniform(items + it);
+    const ScoreParams p = load_uniform(params + item.stream);
+    init_lds(p, lds);
+    score_range<K, TPL, PT>(p, lds, item.begin, item.end);
   }
 }
 
@@ -378,22 +405,22 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
 
 // Per-segment constants f0*T, U*T (FP64) and the bounds of the wild-template
 // test: bound[0] = max |f0 T|, bound[1+k] = max_alpha |U[alpha,k] T| (+inf if
-// an entry is not finite).  `scale` multiplies every constant (1 here).
-// Also clears the near-tie counter.
-__global__ __launch_bounds__(256) void score_prep_kernel(const double *__restrict__ f0, const double *__restrict__ U,
-                                                         int K, int n_seg, double t_sft, double scale, double *seg,
-                                                         int seg_stride, double *bound, unsigned long long *near_tie) {
+// an entry is not finite).  Also clears the near-tie counter.  One workgroup.
+__device__ __forceinline__ void prep_one(const PrepJob &job) {
   __shared__ double red[256];
-  if (threadIdx.x == 0 && near_tie) *near_tie = 0ull;
+  const double *f0 = job.f0, *U = job.U;
+  const int K = job.K, n_seg = job.n_seg, stride = job.seg_stride;
+  const double t_sft = job.t_sft;
+  if (threadIdx.x == 0 && job.near_tie) *job.near_tie = 0ull;
   for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
-    seg[(size_t)a * seg_stride] = (f0[a] * t_sft) * scale;
-    for (int k = 0; k < K; ++k) seg[(size_t)a * seg_stride + 1 + k] = (U[(size_t)a * K + k] * t_sft) * scale;
+    job.seg[(size_t)a * stride] = f0[a] * t_sft;
+    for (int k = 0; k < K; ++k) job.seg[(size_t)a * stride + 1 + k] = U[(size_t)a * K + k] * t_sft;
   }
   for (int col = 0; col <= K; ++col) {
     double m = 0.0;
     for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
       const double v = col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft;
-      const double av = __builtin_fabs(v) * scale;
+      const double av = __builtin_fabs(v);
       m = (av <= 1.7976931348623157e308) ? (av > m ? av : m) : __builtin_inf();
     }
     red[threadIdx.x] = m;
@@ -402,24 +429,58 @@ __global__ __launch_bounds__(256) void score_prep_kernel(const double *__restric
       if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
       __syncthreads();
     }
-    if (threadIdx.x == 0) bound[col] = red[0];
+    if (threadIdx.x == 0) job.bound[col] = red[0];
     __syncthreads();
   }
+}
+
+__global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) { prep_one(job); }
+
+__global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs) {
+  prep_one(load_uniform(jobs + blockIdx.x));
 }
 
 constexpr int tpl_for(int K) {
   const int t = 180 / (2 * K + 3);
   return t > 16 ? 16 : (t < 1 ? 1 : t);
 }
+// a smaller tile for the autotuner: about two thirds of the default slots
+constexpr int tpl_alt(int K) {
+  const int t = tpl_for(K) * 2 / 3;
+  return t < 1 ? 1 : t;
+}
+constexpr bool has_alt(int K) { return K == 8 || K == 16; }
+
+template <typename Kern>
+hipError_t set_lds(Kern kern, size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
 
 template <int K, typename PT>
 hipError_t launch_fast_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
   constexpr int TPL = tpl_for(K);
   auto kern = score_fast_kernel<K, TPL, PT>;
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p);
+  return hipGetLastError();
+}
+
+template <int K, typename PT>
+hipError_t launch_batched_k(const BatchLaunch &b, hipStream_t stream) {
+  hipError_t err;
+  if constexpr (has_alt(K)) {
+    if (b.tpl == tpl_alt(K)) {
+      auto kern = score_batched_kernel<K, tpl_alt(K), PT>;
+      if ((err = set_lds(kern, b.lds)) != hipSuccess) return err;
+      hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
+      return hipGetLastError();
+    }
+  }
+  auto kern = score_batched_kernel<K, tpl_for(K), PT>;
+  if ((err = set_lds(kern, b.lds)) != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
   return hipGetLastError();
 }
 
@@ -431,11 +492,17 @@ hipError_t dispatch_fast(int K, const ScoreParams &p, int grid, size_t lds, hipS
   return err;
 }
 
+template <typename PT, int... Ks>
+hipError_t dispatch_batched(int K, const BatchLaunch &b, hipStream_t stream, std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  ((K == Ks ? (err = launch_batched_k<Ks, PT>(b, stream), true) : false) || ...);
+  return err;
+}
+
 template <typename PT>
 hipError_t launch_validate(const ScoreParams &p, int K, int grid, size_t lds, hipStream_t stream) {
   auto kern = score_validate_kernel<PT>;
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p, K);
   return hipGetLastError();
@@ -443,14 +510,29 @@ hipError_t launch_validate(const ScoreParams &p, int K, int grid, size_t lds, hi
 
 }  // namespace
 
-int score_templates_per_tile(int K) { return tpl_for(K) * SCORE_THREADS; }
+int score_templates_per_lane(int K, bool alt) {
+  switch (K) {
+    case 8: return alt ? tpl_alt(8) : tpl_for(8);
+    case 16: return alt ? tpl_alt(16) : tpl_for(16);
+    default: return tpl_for(K);
+  }
+}
 
-hipError_t launch_score_prep(const double *f0, const double *U, int K, int n_seg, double t_sft, double scale,
-                             double *seg, int seg_stride, double *bound, unsigned long long *near_tie,
-                             hipStream_t stream) {
-  hipLaunchKernelGGL(score_prep_kernel, dim3(1), dim3(256), 0, stream, f0, U, K, n_seg, t_sft, scale, seg,
-                     seg_stride, bound, near_tie);
+hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream) {
+  hipLaunchKernelGGL(score_prep_kernel, dim3(1), dim3(256), 0, stream, job);
   return hipGetLastError();
+}
+
+hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(score_prep_batched_kernel, dim3(n_jobs), dim3(256), 0, stream, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream) {
+  using Ks = std::make_integer_sequence<int, EMRI_MAX_K + 1>;
+  if (b.dtype == EMRI_F32) return dispatch_batched<float>(b.K, b, stream, Ks{});
+  return dispatch_batched<__half>(b.K, b, stream, Ks{});
 }
 
 hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, int grid, size_t lds,

@@ -34,12 +34,51 @@ struct ScoreParams {
   int lo_owner, hi_owner;     // wave that re-zeroes the slot below / above the bin range after a copy (-1: none)
 };
 
-int score_templates_per_tile(int K);
-hipError_t launch_score_prep(const double *f0, const double *U, int K, int n_seg, double t_sft, double scale,
-                             double *seg, int seg_stride, double *bound, unsigned long long *near_tie,
-                             hipStream_t stream);
+// A range of one stream's templates, scored by one workgroup of the batched launch.
+struct BatchItem {
+  int32_t stream;
+  int32_t pad;
+  int64_t begin, end;
+};
+
+// Everything the per-segment constants kernel needs for one stream.
+struct PrepJob {
+  const double *f0, *U;
+  double *seg, *bound;
+  unsigned long long *near_tie;
+  double t_sft;
+  int K, n_seg, seg_stride, pad;
+};
+
+// Launch shape of a batched scoring launch (device tables live in the workspace).
+struct BatchLaunch {
+  const ScoreParams *params;
+  const BatchItem *items;
+  const int *block_items;
+  int grid, K, dtype, tpl;
+  size_t lds;
+};
+
+// Read a small trivially copyable struct from read-only device memory with
+// scalar (constant address space) loads, one dword at a time.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *src) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized structs only");
+  typedef const __attribute__((address_space(4))) uint32_t *cwords;
+  uint32_t w[sizeof(T) / 4];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = ((cwords)src)[i];
+  T out;
+  __builtin_memcpy(&out, w, sizeof(T));
+  return out;
+}
+
+int score_templates_per_lane(int K, bool alt);
+hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream);
+hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, hipStream_t stream);
 hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, int grid, size_t lds,
                         hipStream_t stream);
+hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream);
 
 struct TopkState {
   uint32_t key_prefix;        // bits of the k-th largest key found so far
@@ -53,7 +92,27 @@ struct TopkState {
   uint32_t hist[TOPK_HIST];
 };
 
+// One top-k problem: the statistic, its length, and where state and results live.
+struct TopkJob {
+  const float *stat;
+  int64_t n;
+  int top_k;
+  uint32_t kk;                 // min(n, top_k)
+  TopkState *st;
+  unsigned long long *cand;    // kk candidate (key, index) pairs
+  float *vals;
+  int64_t *idx;
+};
+
+// A device table of jobs (blockIdx.y picks one), or one job by value.
+struct TopkJobs {
+  const TopkJob *jobs;
+  TopkJob single;
+};
+
 size_t topk_workspace_bytes(int top_k);
+TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws);
+hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu_count, hipStream_t stream);
 hipError_t launch_topk(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws, int cu_count,
                        hipStream_t stream);
 

@@ -62,11 +62,20 @@ __device__ __forceinline__ void flush_hist(uint32_t *lh, uint32_t *gh) {
     if (lh[b]) atomicAdd(&gh[b], lh[b]);
 }
 
-__global__ __launch_bounds__(256) void topk_init_kernel(TopkState *st, uint32_t kk) {
+// The job of this workgroup: blockIdx.y indexes the job table, or the single
+// job passed by value when there is no table.
+__device__ __forceinline__ TopkJob job_of(const TopkJobs &J) {
+  if (J.jobs == nullptr) return J.single;
+  return load_uniform(J.jobs + blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void topk_init_kernel(TopkJobs J) {
+  const TopkJob job = job_of(J);
+  TopkState *st = job.st;
   for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) st->hist[b] = 0u;
   if (threadIdx.x == 0) {
     st->key_prefix = 0u;
-    st->need = kk;
+    st->need = job.kk;
     st->idx_prefix = 0u;
     st->idx_need = 0u;
     st->tie_mode = 0u;
@@ -75,27 +84,31 @@ __global__ __launch_bounds__(256) void topk_init_kernel(TopkState *st, uint32_t 
   }
 }
 
-__global__ __launch_bounds__(HIST_THREADS) void topk_hist_key_kernel(const float *__restrict__ stat, int64_t n,
-                                                                     TopkState *st, int pass) {
+__global__ __launch_bounds__(HIST_THREADS) void topk_hist_key_kernel(TopkJobs J, int pass) {
+  const TopkJob job = job_of(J);
+  if (job.kk == 0) return;
   __shared__ uint32_t lh[TOPK_HIST];
   for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) lh[b] = 0u;
   __syncthreads();
   int shift, width;
   key_digit(pass, &shift, &width);
   const int hi = shift + width;
-  const uint32_t prefix = st->key_prefix;
+  const uint32_t prefix = job.st->key_prefix;
   const uint32_t mask = (1u << width) - 1u;
-  for_each_stat(stat, n, [&](int64_t, float v) {
+  for_each_stat(job.stat, job.n, [&](int64_t, float v) {
     const uint32_t k = order_key(v);
     if (hi >= 32 || (k >> hi) == (prefix >> hi)) atomicAdd(&lh[(k >> shift) & mask], 1u);
   });
-  flush_hist(lh, st->hist);
+  flush_hist(lh, job.st->hist);
 }
 
 // One wave scans the histogram from the largest digit down (keys) or from the
 // smallest up (indices) and fixes the digit holding the need-th element.
 template <bool KEYS>
-__global__ __launch_bounds__(64) void topk_select_kernel(TopkState *st, int pass) {
+__global__ __launch_bounds__(64) void topk_select_kernel(TopkJobs J, int pass) {
+  const TopkJob job = job_of(J);
+  TopkState *st = job.st;
+  if (job.kk == 0) return;
   if (!KEYS && st->tie_mode == 0u) return;
   int shift, width;
   if (KEYS) key_digit(pass, &shift, &width); else idx_digit(pass, &shift, &width);
@@ -145,32 +158,35 @@ __global__ __launch_bounds__(64) void topk_select_kernel(TopkState *st, int pass
   for (int b = lane; b < nb; b += 64) st->hist[b] = 0u;
 }
 
-__global__ __launch_bounds__(HIST_THREADS) void topk_hist_idx_kernel(const float *__restrict__ stat, int64_t n,
-                                                                     TopkState *st, int pass) {
-  if (st->tie_mode == 0u) return;
+__global__ __launch_bounds__(HIST_THREADS) void topk_hist_idx_kernel(TopkJobs J, int pass) {
+  const TopkJob job = job_of(J);
+  if (job.kk == 0 || job.st->tie_mode == 0u) return;
   __shared__ uint32_t lh[TOPK_HIST];
   for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) lh[b] = 0u;
   __syncthreads();
   int shift, width;
   idx_digit(pass, &shift, &width);
   const int hi = shift + width;
-  const uint32_t key = st->key_prefix;
-  const uint32_t prefix = st->idx_prefix;
+  const uint32_t key = job.st->key_prefix;
+  const uint32_t prefix = job.st->idx_prefix;
   const uint32_t mask = (1u << width) - 1u;
-  for_each_stat(stat, n, [&](int64_t i, float v) {
+  for_each_stat(job.stat, job.n, [&](int64_t i, float v) {
     const uint32_t u = (uint32_t)i;
     if (order_key(v) == key && (hi >= 31 || (u >> hi) == (prefix >> hi))) atomicAdd(&lh[(u >> shift) & mask], 1u);
   });
-  flush_hist(lh, st->hist);
+  flush_hist(lh, job.st->hist);
 }
 
-__global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(const float *__restrict__ stat, int64_t n,
-                                                                    TopkState *st, unsigned long long *cand,
-                                                                    uint32_t kk) {
+__global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) {
+  const TopkJob job = job_of(J);
+  if (job.kk == 0) return;
+  TopkState *st = job.st;
   const uint32_t key = st->key_prefix;
   const bool tie = st->tie_mode != 0u;
   const uint32_t thr = st->idx_prefix;
-  for_each_stat(stat, n, [&](int64_t i, float v) {
+  const uint32_t kk = job.kk;
+  unsigned long long *cand = job.cand;
+  for_each_stat(job.stat, job.n, [&](int64_t i, float v) {
     const uint32_t k = order_key(v);
     const bool sel = k > key || (k == key && (!tie || (uint32_t)i <= thr));
     if (sel) {
@@ -180,12 +196,13 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(const float 
   });
 }
 
-__global__ __launch_bounds__(1024) void topk_final_kernel(const unsigned long long *cand, uint32_t kk, int top_k,
-                                                          float *vals, int64_t *idx) {
+__global__ __launch_bounds__(1024) void topk_final_kernel(TopkJobs J) {
+  const TopkJob job = job_of(J);
   __shared__ unsigned long long s[EMRI_MAX_TOPK];
+  const int kk = (int)job.kk;
   int p2 = 1;
-  while (p2 < (int)kk) p2 <<= 1;
-  for (int i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < (int)kk ? cand[i] : 0ull;
+  while (p2 < kk) p2 <<= 1;
+  for (int i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < kk ? job.cand[i] : 0ull;
   __syncthreads();
   // bitonic sort, descending
   for (int size = 2; size <= p2; size <<= 1) {
@@ -204,14 +221,14 @@ __global__ __launch_bounds__(1024) void topk_final_kernel(const unsigned long lo
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < top_k; i += blockDim.x) {
-    if (i < (int)kk) {
+  for (int i = threadIdx.x; i < job.top_k; i += blockDim.x) {
+    if (i < kk) {
       const unsigned long long c = s[i];
-      vals[i] = key_value((uint32_t)(c >> 32));
-      idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
+      job.vals[i] = key_value((uint32_t)(c >> 32));
+      job.idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
     } else {
-      vals[i] = -__builtin_inff();
-      idx[i] = -1;
+      job.vals[i] = -__builtin_inff();
+      job.idx[i] = -1;
     }
   }
 }
@@ -222,29 +239,45 @@ size_t topk_workspace_bytes(int top_k) {
   return round_up(sizeof(TopkState), 256) + round_up((size_t)(top_k > 0 ? top_k : 1) * 8, 256);
 }
 
+TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws) {
+  TopkJob job;
+  job.stat = stat;
+  job.n = n;
+  job.top_k = top_k;
+  job.kk = (uint32_t)(n < (int64_t)top_k ? n : (int64_t)top_k);
+  job.st = reinterpret_cast<TopkState *>(ws);
+  job.cand = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + round_up(sizeof(TopkState), 256));
+  job.vals = vals;
+  job.idx = idx;
+  return job;
+}
+
+hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu_count, hipStream_t stream) {
+  if (n_jobs <= 0) return hipSuccess;
+  const int64_t work = (max_n + 4 * HIST_THREADS - 1) / (4 * HIST_THREADS);
+  const int gx = (int)(work < (int64_t)cu_count * 4 ? (work > 0 ? work : 1) : (int64_t)cu_count * 4);
+  const dim3 one(1, n_jobs), hist(gx, n_jobs);
+  hipLaunchKernelGGL(topk_init_kernel, one, dim3(256), 0, stream, J);
+  for (int pass = 0; pass < 3; ++pass) {
+    hipLaunchKernelGGL(topk_hist_key_kernel, hist, dim3(HIST_THREADS), 0, stream, J, pass);
+    hipLaunchKernelGGL(topk_select_kernel<true>, one, dim3(64), 0, stream, J, pass);
+  }
+  for (int pass = 0; pass < 3; ++pass) {
+    hipLaunchKernelGGL(topk_hist_idx_kernel, hist, dim3(HIST_THREADS), 0, stream, J, pass);
+    hipLaunchKernelGGL(topk_select_kernel<false>, one, dim3(64), 0, stream, J, pass);
+  }
+  hipLaunchKernelGGL(topk_compact_kernel, hist, dim3(HIST_THREADS), 0, stream, J);
+  hipLaunchKernelGGL(topk_final_kernel, one, dim3(1024), 0, stream, J);
+  return hipGetLastError();
+}
+
 hipError_t launch_topk(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws, int cu_count,
                        hipStream_t stream) {
   if (top_k <= 0) return hipSuccess;
-  TopkState *st = reinterpret_cast<TopkState *>(ws);
-  unsigned long long *cand =
-      reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + round_up(sizeof(TopkState), 256));
-  const uint32_t kk = (uint32_t)(n < (int64_t)top_k ? n : (int64_t)top_k);
-  if (kk > 0) {
-    const int64_t work = (n + 4 * HIST_THREADS - 1) / (4 * HIST_THREADS);
-    const int grid = (int)(work < (int64_t)cu_count * 4 ? (work > 0 ? work : 1) : (int64_t)cu_count * 4);
-    hipLaunchKernelGGL(topk_init_kernel, dim3(1), dim3(256), 0, stream, st, kk);
-    for (int pass = 0; pass < 3; ++pass) {
-      hipLaunchKernelGGL(topk_hist_key_kernel, dim3(grid), dim3(HIST_THREADS), 0, stream, stat, n, st, pass);
-      hipLaunchKernelGGL(topk_select_kernel<true>, dim3(1), dim3(64), 0, stream, st, pass);
-    }
-    for (int pass = 0; pass < 3; ++pass) {
-      hipLaunchKernelGGL(topk_hist_idx_kernel, dim3(grid), dim3(HIST_THREADS), 0, stream, stat, n, st, pass);
-      hipLaunchKernelGGL(topk_select_kernel<false>, dim3(1), dim3(64), 0, stream, st, pass);
-    }
-    hipLaunchKernelGGL(topk_compact_kernel, dim3(grid), dim3(HIST_THREADS), 0, stream, stat, n, st, cand, kk);
-  }
-  hipLaunchKernelGGL(topk_final_kernel, dim3(1), dim3(1024), 0, stream, cand, kk, top_k, vals, idx);
-  return hipGetLastError();
+  TopkJobs J;
+  J.jobs = nullptr;
+  J.single = make_topk_job(stat, n, top_k, vals, idx, ws);
+  return launch_topk_jobs(J, 1, n, cu_count, stream);
 }
 
 }  // namespace emri

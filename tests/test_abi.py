@@ -154,3 +154,42 @@ def test_build_basis_full_rank_and_k0():
     assert np.abs(X @ U @ U.T - X).max() < 1e-12 * np.abs(X).max()
     f0b, Ub, svb, _, _ = emri.build_basis(F, 0)
     assert np.allclose(f0b, f0) and Ub.shape == (10, 0)
+
+
+def _problem(n_seg=4, n_bins=33, pitch=40, dtype=0, n=10, top_k=2, k_min=0, k_max=-1, reserved=0):
+    pb = emri._Problem()
+    pb.power = _power(n_seg, n_bins, pitch, dtype)
+    pb.f0 = pb.U = pb.coeffs = FAKE
+    pb.n_tmpl = n
+    pb.top_k = top_k
+    pb.k_min, pb.k_max, pb.reserved = k_min, k_max, reserved
+    pb.stat = pb.topk_val = pb.topk_idx = FAKE
+    return pb
+
+
+def test_batched_workspace_size_and_validation():
+    lib = emri.load()
+    arr = (emri._Problem * 3)(_problem(), _problem(n_seg=7, n=0, top_k=0), _problem(n_bins=100, pitch=104))
+    nb = ctypes.c_size_t()
+    assert lib.score_batched_workspace_size(arr, 3, 2, ctypes.byref(nb)) == 0 and nb.value > 0
+    plan = emri._Plan()
+    bad_cases = [
+        ((emri._Problem * 1)(_problem(dtype=1)), 1, 2),          # fine alone ...
+    ]
+    mixed = (emri._Problem * 2)(_problem(), _problem(dtype=1))
+    assert lib.score_batched_workspace_size(mixed, 2, 2, ctypes.byref(nb)) == -1     # mixed dtypes
+    for bad in (_problem(top_k=5000), _problem(n=-1), _problem(k_min=3, k_max=2), _problem(reserved=1),
+                _problem(pitch=36)):
+        one = (emri._Problem * 1)(bad)
+        assert lib.score_batched_workspace_size(one, 1, 2, ctypes.byref(nb)) == -1
+        assert lib.score_batched_plan(one, 1, 2, None, FAKE, 1 << 30, ctypes.byref(plan), None) == -1
+    assert lib.score_batched_workspace_size(arr, 3, 33, ctypes.byref(nb)) == -1
+    opts = emri._BatchOpts(3, 0)
+    assert lib.score_batched_plan(arr, 3, 2, ctypes.byref(opts), FAKE, 1 << 30, ctypes.byref(plan), None) == -1
+    assert lib.score_batched_plan(arr, 3, 2, None, FAKE + 16, 1 << 30, ctypes.byref(plan), None) == -1
+    assert lib.score_batched_run(ctypes.byref(emri._Plan()), None) == -1               # not a plan
+
+
+def test_batched_tile_options():
+    assert emri.batched_tile_options(8)[0] == 9 and len(emri.batched_tile_options(8)) == 2
+    assert len(emri.batched_tile_options(5)) == 1
