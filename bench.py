@@ -80,6 +80,18 @@ def cpu_baseline(P, f0, U, C, t_sft, n_sample: int) -> dict:
                       f"{cores} worker processes, {wall:.2f} s wall"}
 
 
+def copy_calibration(nbytes: int) -> int:
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the kernel's."""
+    import torch
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes}), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +100,11 @@ def main() -> int:
     ap.add_argument("--templates", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1 << 21)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (reference for traffic counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(templates would shard across GPUs with one top-k exchange; see the design notes)",

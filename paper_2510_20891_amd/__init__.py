@@ -155,7 +155,8 @@ class Spectrogram:
 
 
 def default_row_pitch(n_bins: int) -> int:
-    return (n_bins + 7) // 8 * 8
+    """Smallest multiple of 8 above n_bins: the padding element lets scoring stage several rows per step."""
+    return (n_bins + 8) // 8 * 8
 
 
 def spectrogram_from_power(power, t_sft: float, dtype: str = "f32"):

@@ -100,24 +100,10 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   if (workspace_bytes < L.total)
     return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
 
-  // LDS staging geometry: a 16-byte lead-in, the row of n_bins elements rounded
-  // up to 16 bytes and copied in 1 KB wave chunks, and a 16-byte tail; two to
-  // four buffers.  The slots just below k_min and above k_max hold zeros.
-  const int eb = elem_bytes(power->dtype);
-  const int copy_bytes = (int)round_up((size_t)power->n_bins * eb, 16);
-  const int row_chunks = (copy_bytes + 1023) / 1024;
-  const int buf_bytes = SCORE_LDS_LEAD + row_chunks * 1024 + 16;
-  // two halves of G = 1, 2 or 4 row buffers, as many as fit
-  const int fit = (int)(kLdsLimit / (size_t)buf_bytes);
-  const int nbuf = fit >= 8 ? 8 : (fit >= 4 ? 4 : 2);
-  if ((size_t)nbuf * buf_bytes > kLdsLimit)
+  // LDS staging geometry: two halves of G consecutive rows (see score_internal.h)
+  Staging sg;
+  if (!make_staging(power->n_bins, power->row_pitch, elem_bytes(power->dtype), k_min, k_max, 0, kLdsLimit, &sg))
     return fail(EMRI_EUNSUPPORTED, "a spectrogram row of %d bins does not fit twice in LDS", power->n_bins);
-  const size_t lds = (size_t)nbuf * buf_bytes;
-  auto owner = [&](int bin) {       // wave whose copy writes bin `bin`, or -1
-    if (bin < 0) return -1;
-    const int chunk = bin * eb / 1024;
-    return chunk < row_chunks ? chunk % (SCORE_THREADS / 64) : -1;
-  };
   int cus = 0;
   if ((st = device_cu_count(&cus)) != EMRI_OK) return st;
 
@@ -157,22 +143,19 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     p.seg_stride = L.seg_stride;
     p.k_min = k_min;
     p.k_max = k_max;
-    p.row_bytes_pitch = power->row_pitch * eb;
-    p.copy_bytes = copy_bytes;
-    p.row_chunks = row_chunks;
-    p.buf_bytes = buf_bytes;
-    p.nbuf = nbuf;
-    p.lo_owner = owner(k_min - 1);
-    p.hi_owner = owner(k_max + 1);
+    p.pitch_bytes = sg.pitch_bytes;
+    p.G = sg.G;
+    p.half_bytes = sg.half_bytes;
+    p.slot_owner = sg.slot_owner;
     const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;
     const int grid = (int)(units < cus ? units : cus);
     p.per_block = (n_tmpl + grid - 1) / grid;
     if (power->n_seg == 0) {
       // no segment contributes: every statistic is zero; reuse the validation
       // kernel, whose segment loop is then empty
-      err = launch_score(p, K, power->dtype, true, grid, lds, stream);
+      err = launch_score(p, K, power->dtype, true, grid, sg.lds, stream);
     } else {
-      err = launch_score(p, K, power->dtype, validate, grid, lds, stream);
+      err = launch_score(p, K, power->dtype, validate, grid, sg.lds, stream);
     }
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score launch: %s", hipGetErrorString(err));
   }

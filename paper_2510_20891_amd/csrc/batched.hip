@@ -36,19 +36,6 @@ static_assert(sizeof(PlanData) <= sizeof(emri_batch_plan), "plan does not fit");
 
 int elem_bytes(int dtype) { return dtype == EMRI_F16 ? 2 : 4; }
 
-struct Geometry {
-  int copy_bytes, row_chunks, buf_bytes;
-};
-
-Geometry geometry(const emri_power &pw) {
-  Geometry g;
-  const int eb = elem_bytes(pw.dtype);
-  g.copy_bytes = (int)round_up((size_t)pw.n_bins * eb, 16);
-  g.row_chunks = (g.copy_bytes + 1023) / 1024;
-  g.buf_bytes = SCORE_LDS_LEAD + g.row_chunks * 1024 + 16;
-  return g;
-}
-
 int check_problem(const emri_problem &pb, int i, int K, int dtype) {
   const emri_power &pw = pb.power;
   if (pw.dtype != EMRI_F32 && pw.dtype != EMRI_F16) return fail(EMRI_EINVAL, "problem %d: unknown power dtype", i);
@@ -183,17 +170,18 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   int tpl = 0, st = resolve_tpl(K, o.templates_per_lane, &tpl);
   if (st) return st;
 
-  // staging geometry: the same number of rows per step for every problem,
-  // the most that fits the largest row (or the requested count)
-  int max_buf = SCORE_LDS_LEAD + 1024 + 16;
-  for (int i = 0; i < n_problems; ++i) max_buf = std::max(max_buf, geometry(problems[i].power).buf_bytes);
-  const int fit = (int)(kLdsLimit / (size_t)max_buf);
-  int G = fit >= 8 ? 4 : (fit >= 4 ? 2 : 1);
-  if (fit < 2) return fail(EMRI_EUNSUPPORTED, "a spectrogram row does not fit twice in LDS");
-  if (o.rows_per_step != 0) {
-    if (2 * o.rows_per_step > fit)
-      return fail(EMRI_EUNSUPPORTED, "rows_per_step %d does not fit in LDS for these rows", o.rows_per_step);
-    G = o.rows_per_step;
+  // staging geometry per problem (the requested rows per step, or the most
+  // that fit); the launch takes the largest LDS footprint
+  std::vector<Staging> stg(n_problems);
+  size_t lds = 0;
+  for (int i = 0; i < n_problems; ++i) {
+    const emri_power &pw = problems[i].power;
+    const int k_max = problems[i].k_max < 0 ? pw.n_bins - 1 : problems[i].k_max;
+    if (!make_staging(pw.n_bins, pw.row_pitch, elem_bytes(pw.dtype), problems[i].k_min, k_max, o.rows_per_step,
+                      kLdsLimit, &stg[i]))
+      return fail(EMRI_EUNSUPPORTED, "problem %d: %d rows per step of %d bins do not fit in LDS", i,
+                  o.rows_per_step ? o.rows_per_step : 1, pw.n_bins);
+    lds = std::max(lds, stg[i].lds);
   }
   int cus = 0;
   if ((st = batch_grid(&cus)) != EMRI_OK) return st;
@@ -211,14 +199,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   int64_t max_topk_n = 0;
   for (int i = 0; i < n_problems; ++i) {
     const emri_problem &pb = problems[i];
-    const Geometry g = geometry(pb.power);
-    const int eb = elem_bytes(pb.power.dtype);
     const int k_max = pb.k_max < 0 ? pb.power.n_bins - 1 : pb.k_max;
-    auto owner = [&](int bin) {
-      if (bin < 0) return -1;
-      const int chunk = bin * eb / 1024;
-      return chunk < g.row_chunks ? chunk % (SCORE_THREADS / 64) : -1;
-    };
     ScoreParams &p = params[i];
     std::memset(&p, 0, sizeof p);
     p.power = pb.power.data;
@@ -231,13 +212,10 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     p.seg_stride = seg_stride_of(K);
     p.k_min = pb.k_min;
     p.k_max = k_max;
-    p.row_bytes_pitch = pb.power.row_pitch * eb;
-    p.copy_bytes = g.copy_bytes;
-    p.row_chunks = g.row_chunks;
-    p.buf_bytes = g.buf_bytes;
-    p.nbuf = 2 * G;
-    p.lo_owner = owner(pb.k_min - 1);
-    p.hi_owner = owner(k_max + 1);
+    p.pitch_bytes = stg[i].pitch_bytes;
+    p.G = stg[i].G;
+    p.half_bytes = stg[i].half_bytes;
+    p.slot_owner = stg[i].slot_owner;
     PrepJob &pj = preps[i];
     std::memset(&pj, 0, sizeof pj);
     pj.f0 = pb.f0;
@@ -323,7 +301,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.launch.K = K;
   pd.launch.dtype = dtype;
   pd.launch.tpl = tpl;
-  pd.launch.lds = (size_t)(2 * G) * max_buf;
+  pd.launch.lds = lds;
   pd.prep_jobs = reinterpret_cast<const PrepJob *>(ws + L.prep);
   pd.topk_jobs = reinterpret_cast<const TopkJob *>(ws + L.topk_jobs);
   pd.n_items = (int)items.size();

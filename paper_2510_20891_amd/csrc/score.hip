@@ -84,11 +84,12 @@ struct BufConst {
   int base;      // LDS element index (address / E) of bin 0
 };
 
+// Row buffer b of LDS half `half`: bin 0 sits pitch_bytes * b after the half's lead-in.
 template <typename PT>
-__device__ __forceinline__ BufConst buffer_consts(const ScoreParams &p, const unsigned char *lds, int buf) {
+__device__ __forceinline__ BufConst buffer_consts(const ScoreParams &p, const unsigned char *lds, int half, int b) {
   constexpr int E = Elem<PT>::bytes;
-  // absolute LDS byte address of bin 0, in elements (even: buffers are 16-byte aligned)
-  const int base = (lds_address(lds) + buf * p.buf_bytes + kLeadIn) / E;
+  // absolute LDS byte address of bin 0, in elements (even: 16-byte aligned)
+  const int base = (int)(((unsigned)lds_address(lds) + (unsigned)(half * p.half_bytes + kLeadIn + b * p.pitch_bytes)) / E);
   BufConst bc;
   bc.base = base;
   bc.magic = 6755399441055744.0 + (double)base;     // 1.5*2^52 + base
@@ -102,86 +103,75 @@ __device__ __forceinline__ int low_word(double y) { return (int)(unsigned)__doub
 // Wave index as a wave-uniform (scalar) value.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-// Rows are staged in LDS through 2G buffers (G = p.nbuf / 2 rows per step):
-// during step s the rows [sG, sG+G) are read from buffer half s & 1 while the
-// copies of the next G rows fill the other half; a step ends by waiting for
-// its copies and a workgroup barrier.  Wave w copies the 1 KB chunks w, w+8,
-// w+16, ... of every row.  A lane's source offset inside a row is the same for
-// every row, so it is computed once: off0 for every chunk but the wave's last,
-// off_last (clamped to the row's end) for the last one.
-struct RowPipe {
-  int G;         // rows per step
-  int per_row;   // copies this wave issues per row
-  int off0;      // lane's byte offset of its 16 bytes in chunk `wave`
-  int off_last;  // same for this wave's last chunk, relative to that chunk's start offset
+// Staging pipeline.  A step stages G consecutive rows into one LDS half while
+// the other half is gathered from; it ends with a wait for this wave's copies,
+// the re-zeroing of the zero slots this wave's copies overwrote, and a
+// workgroup barrier.  The G rows are one contiguous block in HBM and in LDS, so
+// wave w copies its 1 KB chunks w, w+8, w+16, ... with one instruction each.
+struct Pipe {
+  int wave;
+  int lane_off;      // lane * 16: this lane's bytes within a chunk
+  int slot_off;      // byte offset (from the half's start) of this lane's zero slot
+  bool slot_mine;    // this lane re-zeroes slot_off after each copy
 };
 
-// Issue the asynchronous copy of power row `alpha` into LDS buffer `buf`.
-// Every lane copies 16 bytes; lanes past the row re-read its last 16 bytes and
-// write them past the row's end inside the buffer, where no gather looks.
-__device__ __forceinline__ void issue_row_copy(const ScoreParams &p, const RowPipe &rp, int alpha,
-                                               unsigned char *lds, int buf) {
-  const int wave = wave_id();
-  const char *row = reinterpret_cast<const char *>(p.power) + (size_t)alpha * (size_t)p.row_bytes_pitch;
-  unsigned char *dst = lds + buf * p.buf_bytes + kLeadIn + wave * 1024;
-  for (int i = 0; i < rp.per_row; ++i) {
-    const unsigned voff = (unsigned)(i + 1 < rp.per_row ? rp.off0 : rp.off_last);
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(row + (size_t)i * 8192 + voff),
-                                     (__attribute__((address_space(3))) void *)(dst + i * 8192), 16, 0, 0);
+template <typename PT>
+__device__ __forceinline__ Pipe pipe_init(const ScoreParams &p) {
+  constexpr int E = Elem<PT>::bytes;
+  Pipe pp;
+  pp.wave = wave_id();
+  const int lane = (int)(threadIdx.x & 63);
+  pp.lane_off = lane * 16;
+  pp.slot_mine = false;
+  pp.slot_off = 0;
+  if (lane < 2 * p.G) {
+    const int bin = (lane & 1) ? p.k_max + 1 : p.k_min - 1;
+    pp.slot_off = kLeadIn + (lane >> 1) * p.pitch_bytes + E * bin;
+    pp.slot_mine = (int)((p.slot_owner >> (4 * lane)) & 15u) == pp.wave;
+  }
+  return pp;
+}
+
+// Queue the copies of rows [r0, r0 + G) (clipped to n_seg) into half `half`.
+// The final chunk's lanes that would read past the block re-read its last 16
+// bytes; what they write lands in the half's slack, which no gather reads.
+__device__ __forceinline__ void pipe_issue(const ScoreParams &p, const Pipe &pp, unsigned char *lds, int r0,
+                                           int half) {
+  if (r0 >= p.n_seg) return;
+  const int rows = p.n_seg - r0 < p.G ? p.n_seg - r0 : p.G;
+  const int bytes = rows * p.pitch_bytes;
+  const int last = (bytes - 1) >> 10;
+  const char *src = reinterpret_cast<const char *>(p.power) + (size_t)r0 * (size_t)p.pitch_bytes;
+  unsigned char *dst = lds + half * p.half_bytes + kLeadIn;
+  for (int c = pp.wave; c < last; c += SCORE_WAVES)
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + c * 1024 + pp.lane_off),
+                                     (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
+  if ((last & (SCORE_WAVES - 1)) == pp.wave) {
+    const int lim = bytes - 16 - last * 1024;
+    const int off = pp.lane_off < lim ? pp.lane_off : lim;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + last * 1024 + off),
+                                     (__attribute__((address_space(3))) void *)(dst + last * 1024), 16, 0, 0);
   }
 }
 
-// Zero slots just outside [k_min, k_max].  A slot inside the copied part of a
-// row is rewritten after every copy by the wave whose copy covers it; a slot
-// outside it is written once at kernel start.
+// Wait for this wave's copies, re-zero the slots they overwrote in half `half`,
+// and publish the rows to the workgroup.
 template <typename PT>
-__device__ __forceinline__ void zero_slots_after_copy(const ScoreParams &p, unsigned char *lds, int buf) {
-  const int wave = wave_id();
-  if ((threadIdx.x & 63) != 0) return;
-  if (wave == p.lo_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).lo);
-  if (wave == p.hi_owner) Elem<PT>::zero(Elem<PT>::bytes * buffer_consts<PT>(p, lds, buf).hi);
-}
-
-__device__ __forceinline__ RowPipe pipe_init(const ScoreParams &p) {
-  RowPipe rp;
-  rp.G = p.nbuf >> 1;
-  const int wave = wave_id();
-  rp.per_row = wave < p.row_chunks ? (p.row_chunks - wave + SCORE_THREADS / 64 - 1) / (SCORE_THREADS / 64) : 0;
-  rp.off0 = (wave * 64 + (int)(threadIdx.x & 63)) * 16;
-  const int last_start = (rp.per_row > 0 ? rp.per_row - 1 : 0) * 8192;
-  const int last_off = rp.off0 + last_start;
-  rp.off_last = (last_off < p.copy_bytes ? last_off : p.copy_bytes - 16) - last_start;
-  return rp;
-}
-
-// Queue the copies of rows [first, first + G) into buffer half `half`.
-__device__ __forceinline__ void pipe_issue(const ScoreParams &p, const RowPipe &rp, unsigned char *lds, int first,
-                                           int half) {
-  for (int i = 0; i < rp.G; ++i)
-    if (first + i < p.n_seg) issue_row_copy(p, rp, first + i, lds, half * rp.G + i);
-}
-
-// Wait for this wave's copies, re-zero the range slots of half `half`, and
-// publish the rows to the workgroup.
-template <typename PT>
-__device__ __forceinline__ void pipe_publish(const ScoreParams &p, const RowPipe &rp, unsigned char *lds, int half) {
+__device__ __forceinline__ void pipe_publish(const ScoreParams &p, const Pipe &pp, unsigned char *lds, int half) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  for (int i = 0; i < rp.G; ++i) zero_slots_after_copy<PT>(p, lds, half * rp.G + i);
+  if (pp.slot_mine) Elem<PT>::zero(lds_address(lds) + half * p.half_bytes + pp.slot_off);
   __syncthreads();
 }
 
+// Zero the three 16-byte areas no copy writes: the lead-in of each half (the
+// slot below bin 0 of its first row) and the tail after the second half.
 __device__ __forceinline__ void init_lds(const ScoreParams &p, unsigned char *lds) {
-  // lead-in and tail of every buffer
-  for (int b = 0; b < p.nbuf; ++b) {
-    unsigned char *buf = lds + b * p.buf_bytes;
-    for (int i = threadIdx.x; i < kLeadIn; i += SCORE_THREADS) buf[i] = 0;
-    for (int i = kLeadIn + p.row_chunks * 1024 + threadIdx.x; i < p.buf_bytes; i += SCORE_THREADS) buf[i] = 0;
-  }
+  if (threadIdx.x < 3 * kLeadIn) lds[(threadIdx.x / kLeadIn) * p.half_bytes + threadIdx.x % kLeadIn] = 0;
 }
 
 template <int K>
-__device__ __forceinline__ void load_segment(const ScoreParams &p, int a, double &f0t, double (&ut)[K > 0 ? K : 1]) {
-  const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
+__device__ __forceinline__ void load_segment(const double *sp, double &f0t, double (&ut)[K > 0 ? K : 1]) {
+  const_dptr sc = (const_dptr)sp;
   f0t = sc[0];
 #pragma unroll
   for (int k = 0; k < K; ++k) ut[k] = sc[1 + k];
@@ -220,21 +210,22 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   float acc[TPL];
 #pragma unroll
   for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
-  const RowPipe rp = pipe_init(p);
-  pipe_issue(p, rp, lds, 0, 0);
-  pipe_publish<PT>(p, rp, lds, 0);
+  const Pipe pp = pipe_init<PT>(p);
+  const int G = p.G;
+  pipe_issue(p, pp, lds, 0, 0);
+  pipe_publish<PT>(p, pp, lds, 0);
   int addr[TPL];
   double f0t, ut[K > 0 ? K : 1];
   if (p.n_seg > 0) {
-    load_segment<K>(p, 0, f0t, ut);
-    bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, 0), addr);
-    load_segment<K>(p, p.n_seg > 1 ? 1 : 0, f0t, ut);
+    load_segment<K>(p.seg, f0t, ut);
+    bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, 0, 0), addr);
+    load_segment<K>(p.seg + (p.n_seg > 1 ? p.seg_stride : 0), f0t, ut);
   }
   __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0): nothing scalar in flight entering the loop
   int half = 0;
-  for (int r0 = 0; r0 < p.n_seg; r0 += rp.G) {
-    pipe_issue(p, rp, lds, r0 + rp.G, half ^ 1);
-    for (int i = 0; i < rp.G; ++i) {
+  for (int r0 = 0; r0 < p.n_seg; r0 += G) {
+    pipe_issue(p, pp, lds, r0 + G, half ^ 1);
+    for (int i = 0; i < G; ++i) {
       const int r = r0 + i;
       if (r >= p.n_seg) break;
       float v[TPL];
@@ -243,10 +234,10 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
       // Bins of segment r+1 (for the last segment this computes clamped, unused
       // addresses), then the constants of segment r+2, issued after the FMAs so
       // that the wait for this segment's gathers also covers them.
-      const int nb = i + 1 < rp.G ? half * rp.G + i + 1 : (half ^ 1) * rp.G;
-      bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, nb), addr);
+      const int nh = i + 1 < G ? half : half ^ 1, nb = i + 1 < G ? i + 1 : 0;
+      bin_addresses<K, TPL, WILD>(c, f0t, ut, buffer_consts<PT>(p, lds, nh, nb), addr);
       __builtin_amdgcn_sched_barrier(0);
-      load_segment<K>(p, r + 2 < p.n_seg ? r + 2 : p.n_seg - 1, f0t, ut);
+      load_segment<K>(p.seg + (size_t)(r + 2 < p.n_seg ? r + 2 : p.n_seg - 1) * p.seg_stride, f0t, ut);
       // lgkmcnt(0): this segment's gathers and the scalar loads just issued;
       // the next segment's FMAs then start without waiting for its own gathers.
       __builtin_amdgcn_s_waitcnt(0xC07F);
@@ -261,7 +252,7 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
         }
       }
     }
-    pipe_publish<PT>(p, rp, lds, half ^ 1);
+    pipe_publish<PT>(p, pp, lds, half ^ 1);
     half ^= 1;
   }
 }
@@ -367,13 +358,13 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
     for (int k = 0; k < EMRI_MAX_K; ++k) c[k] = (k < K && live) ? (double)p.coeffs[(size_t)j * K + k] : 0.0;
     double sum = 0.0;
     float acc = 0.0f;
-    const RowPipe rp = pipe_init(p);
-    pipe_issue(p, rp, lds, 0, 0);
-    pipe_publish<PT>(p, rp, lds, 0);
+    const Pipe pp = pipe_init<PT>(p);
+    pipe_issue(p, pp, lds, 0, 0);
+    pipe_publish<PT>(p, pp, lds, 0);
     int half = 0;
-    for (int r0 = 0; r0 < p.n_seg; r0 += rp.G) {
-      pipe_issue(p, rp, lds, r0 + rp.G, half ^ 1);
-      for (int i = 0; i < rp.G && r0 + i < p.n_seg; ++i) {
+    for (int r0 = 0; r0 < p.n_seg; r0 += p.G) {
+      pipe_issue(p, pp, lds, r0 + p.G, half ^ 1);
+      for (int i = 0; i < p.G && r0 + i < p.n_seg; ++i) {
         const int a = r0 + i;
         const_dptr sc = (const_dptr)(p.seg + (size_t)a * p.seg_stride);
         double y = sc[0];
@@ -385,7 +376,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
           if (__builtin_fabs(fr - 0.5) < kNearTie) ++near;
         }
         const double ys = (__builtin_fabs(y) < kWildLimit) ? y : -2.0;
-        const BufConst bc = buffer_consts<PT>(p, lds, half * rp.G + i);
+        const BufConst bc = buffer_consts<PT>(p, lds, half, i);
         const int word = low_word(ys + bc.magic);
         const int b = word - bc.base;
         acc += Elem<PT>::load(E * clamp_i32(word, bc.lo, bc.hi));
@@ -395,7 +386,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
           acc = 0.0f;
         }
       }
-      pipe_publish<PT>(p, rp, lds, half ^ 1);
+      pipe_publish<PT>(p, pp, lds, half ^ 1);
       half ^= 1;
     }
     if (live && p.stat) p.stat[j] = (float)sum;
@@ -543,6 +534,41 @@ hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, i
   using Ks = std::make_integer_sequence<int, EMRI_MAX_K + 1>;
   if (dtype == EMRI_F32) return dispatch_fast<float>(K, p, grid, lds, stream, Ks{});
   return dispatch_fast<__half>(K, p, grid, lds, stream, Ks{});
+}
+
+bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_max, int rows_per_step,
+                  size_t lds_limit, Staging *out) {
+  const int pitch_bytes = row_pitch * elem_bytes;
+  auto half_of = [&](int G) { return (size_t)SCORE_LDS_LEAD + round_up((size_t)G * pitch_bytes, 1024); };
+  auto fits = [&](int G) { return 2 * half_of(G) + SCORE_LDS_LEAD <= lds_limit; };
+  const bool padded = row_pitch > n_bins;      // a row's padding holds the next row's slot below bin 0
+  int G = 0;
+  if (rows_per_step != 0) {
+    if ((rows_per_step > 1 && !padded) || !fits(rows_per_step)) return false;
+    G = rows_per_step;
+  } else {
+    for (int g : {4, 2, 1})
+      if ((g == 1 || padded) && fits(g)) {
+        G = g;
+        break;
+      }
+    if (G == 0) return false;
+  }
+  const int half = (int)half_of(G);
+  const int copied = half - SCORE_LDS_LEAD;     // bytes a full step writes
+  uint32_t owner = 0xffffffffu;
+  for (int j = 0; j < 2 * G; ++j) {
+    const int bin = (j & 1) ? k_max + 1 : k_min - 1;
+    const int rel = (j >> 1) * pitch_bytes + elem_bytes * bin;
+    const uint32_t w = (rel >= 0 && rel < copied) ? (uint32_t)((rel >> 10) % SCORE_WAVES) : 15u;
+    owner = (owner & ~(15u << (4 * j))) | (w << (4 * j));
+  }
+  out->G = G;
+  out->pitch_bytes = pitch_bytes;
+  out->half_bytes = half;
+  out->slot_owner = owner;
+  out->lds = 2 * (size_t)half + SCORE_LDS_LEAD;
+  return true;
 }
 
 }  // namespace emri

@@ -11,7 +11,8 @@ constexpr int SCORE_THREADS = 512;   // one persistent workgroup of 8 waves per 
 constexpr int EMRI_MAX_K = 32;
 constexpr int EMRI_MAX_TOPK = 4096;
 constexpr int TOPK_HIST = 2048;
-constexpr int SCORE_LDS_LEAD = 16;   // bytes ahead of bin 0 in each LDS row buffer
+constexpr int SCORE_LDS_LEAD = 16;   // bytes ahead of each LDS half's first row
+constexpr int SCORE_WAVES = SCORE_THREADS / 64;
 
 struct ScoreParams {
   const void *power;          // spectrogram rows (FP32 or FP16)
@@ -26,13 +27,27 @@ struct ScoreParams {
   int n_seg;
   int seg_stride;
   int k_min, k_max;
-  int row_bytes_pitch;        // bytes between spectrogram rows
-  int copy_bytes;             // bytes of a row copied to LDS (n_bins elements, 16-byte multiple)
-  int row_chunks;             // 1 KB wave copies per row
-  int buf_bytes;              // bytes per LDS row buffer (multiple of 16)
-  int nbuf;                   // LDS row buffers: 2, 4 or 8 (two halves of G = nbuf/2 rows)
-  int lo_owner, hi_owner;     // wave that re-zeroes the slot below / above the bin range after a copy (-1: none)
+  int pitch_bytes;            // bytes between rows, in HBM and between LDS row buffers
+  int G;                      // rows per staging step (1, 2 or 4)
+  int half_bytes;             // bytes of one LDS half: lead-in + G rows rounded up to 1 KB
+  uint32_t slot_owner;        // nibble j: wave that re-zeroes zero slot j after a copy (>= 8: none)
 };
+
+// LDS staging of spectrogram rows.  Two halves, each a 16-byte lead-in followed
+// by G consecutive rows exactly as they lie in HBM (pitch_bytes apart), copied
+// as one contiguous block in 1 KB wave chunks.  Zero slot j (j < 2G) belongs to
+// row buffer j/2: the bin below k_min (j even) or above k_max (j odd).
+struct Staging {
+  int G, pitch_bytes, half_bytes;
+  uint32_t slot_owner;
+  size_t lds;                 // bytes of dynamic LDS (both halves and a 16-byte tail)
+};
+
+// Staging geometry for one spectrogram and bin range.  G = rows_per_step if it
+// is nonzero, else the most of 4, 2, 1 that fit; G > 1 needs a padding element
+// after every row (row_pitch > n_bins).  Returns false if it does not fit.
+bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_max, int rows_per_step,
+                  size_t lds_limit, Staging *out);
 
 // A range of one stream's templates, scored by one workgroup of the batched launch.
 struct BatchItem {

@@ -335,3 +335,40 @@ def test_one_year_full_size_sampled(gpu_lib):
     got = set(_np(res["topk_idx"]).tolist())
     assert set(_np(si_[: st["top_k"]]).tolist()) == got or np.isclose(kth, float(sv_[st["top_k"]]))
     assert np.array_equal(_np(res["topk_val"]), stat[_np(res["topk_idx"])])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("n_seg,n_bins,pitch,k_range", [
+    (7, 256, 256, (0, None)),       # no padding: one row per step; rows of exactly 1 KB (f32)
+    (9, 256, 264, (0, None)),       # padded: several rows per step, ragged final step
+    (5, 513, 520, (3, 500)),        # bin range inside the row
+    (13, 1000, 1000, (1, 998)),     # no padding, interior range
+    (11, 4321, 4328, (0, None)),    # config-0 row length
+])
+def test_staging_geometries_with_dirty_padding(gpu_lib, dtype, n_seg, n_bins, pitch, k_range):
+    """Row padding holds huge values that must never be gathered; fast and validation kernels
+    agree bit for bit, and both match the oracle."""
+    import torch
+    emri = gpu_lib
+    g = np.random.default_rng(n_bins + pitch)
+    t = 1000.0
+    P = g.exponential(size=(n_seg, n_bins))
+    data = np.full((n_seg, pitch), 3.0e4)
+    data[:, :n_bins] = P
+    tdtype = torch.float32 if dtype == "f32" else torch.float16
+    spec = emri.Spectrogram(_t(data).to(tdtype), n_bins, t)
+    P_used = _np(spec.power()).astype(np.float64)
+    K = 3
+    f0 = g.uniform(0.1, 0.9, n_seg) * n_bins / t
+    U = g.standard_normal((n_seg, K)) * (n_bins / 6 / t)
+    C = g.uniform(-1.5, 1.5, (3000, K)).astype(np.float32)
+    k_min, k_max = k_range[0], (n_bins - 1 if k_range[1] is None else k_range[1])
+    args = (spec, _t(f0), _t(U), _t(C), 16)
+    fast = emri.score_tracks(*args, k_min=k_min, k_max=k_max)
+    val = emri.score_tracks(*args, k_min=k_min, k_max=k_max, want_bins=True, want_near_tie=True)
+    torch.cuda.synchronize()
+    fast, val = ({k: _np(v) for k, v in r.items()} for r in (fast, val))
+    assert np.array_equal(fast["stat"], val["stat"])
+    o = oracle.score_tracks(P_used, f0, U, C, t, 16, k_min, k_max, want_bins=True)
+    check_against_oracle(P_used, f0, U, C, t, val, o, k_min, k_max)
+    assert fast["stat"].max() < 3.0e4 * 0.5
