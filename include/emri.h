@@ -56,11 +56,19 @@ typedef struct {
   double t_sft;           /* segment duration T_SFT in seconds; bin b is at b / T_SFT Hz */
 } emri_power;
 
+/* Arithmetic of the track contraction sum_k c_k U[alpha, k] T_SFT. */
+typedef enum {
+  EMRI_PLAIN = 0,         /* FP64 fused multiply-adds on the vector units                     */
+  EMRI_MIXED = 1          /* BF16 matrix cores on 3-piece split operands, FP32 accumulation;  */
+                          /* f0 T_SFT and the rounding to a bin stay FP64 (1 <= K <= 16)      */
+} emri_precision;
+
 /* Options for score_tracks; a NULL pointer selects the defaults. */
 typedef struct {
   int32_t k_min;          /* lowest bin that contributes (default 0)                      */
   int32_t k_max;          /* highest bin that contributes; < 0 means n_bins - 1 (default) */
-  int32_t reserved[6];    /* must be zero                                                 */
+  int32_t precision;      /* emri_precision (default EMRI_PLAIN)                          */
+  int32_t reserved[5];    /* must be zero                                                 */
 } score_opts;
 
 /*
@@ -200,7 +208,8 @@ typedef struct {
 typedef struct {
   int32_t rows_per_step;       /* spectrogram rows staged per step: 0 = as many as fit, or 1, 2, 4 */
   int32_t templates_per_lane;  /* 0 = default; otherwise a value score_batched_tile_options lists  */
-  int32_t reserved[6];         /* must be zero                                                     */
+  int32_t precision;           /* emri_precision (EMRI_MIXED stages 4 rows per step)               */
+  int32_t reserved[5];         /* must be zero                                                     */
 } batch_opts;
 
 typedef struct {

@@ -23,6 +23,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libemri.so")
 
 F32, F16 = 0, 1
+PLAIN, MIXED = 0, 1
+_PRECISIONS = {"plain": PLAIN, "mixed": MIXED}
 _DTYPES = {"f32": F32, "f16": F16}
 MAX_K = 32
 MAX_TOPK = 4096
@@ -42,7 +44,8 @@ class _Power(ctypes.Structure):
 
 
 class _Opts(ctypes.Structure):
-    _fields_ = [("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 _vp, _i32, _i64, _dbl, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -55,7 +58,7 @@ class _Problem(ctypes.Structure):
 
 
 class _BatchOpts(ctypes.Structure):
-    _fields_ = [("rows_per_step", _i32), ("templates_per_lane", _i32), ("reserved", _i32 * 6)]
+    _fields_ = [("rows_per_step", _i32), ("templates_per_lane", _i32), ("precision", _i32), ("reserved", _i32 * 5)]
 
 
 class _Plan(ctypes.Structure):
@@ -231,10 +234,12 @@ _default_ws = Workspace()
 
 def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: bool = True,
                  want_bins: bool = False, want_near_tie: bool = False, k_min: int = 0, k_max: int = -1,
-                 out: dict | None = None, workspace: Workspace | None = None, stream=None) -> dict:
+                 precision: str = "plain", out: dict | None = None, workspace: Workspace | None = None,
+                 stream=None) -> dict:
     """Nearest-bin statistic and top-k of a coefficient batch (device tensors).
 
     f0: (n_seg,) float64;  U: (n_seg, K) float64;  coeffs: (n_tmpl, K) float32.
+    precision: "plain" (FP64 contraction) or "mixed" (BF16-split matrix cores, FP64 rounding).
     Returns tensors: ``stat`` (n_tmpl,) float32 if want_stat, ``topk_val`` (top_k,),
     ``topk_idx`` (top_k,) int64, and ``bins`` / ``n_near_tie`` if requested.
     ``out`` may hold preallocated tensors under the same keys.
@@ -260,7 +265,7 @@ def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: boo
         res["n_near_tie"] = torch.zeros(2, dtype=torch.int64, device=dev)
     nbytes = score_tracks_workspace_size(spec, K, n_tmpl, top_k, not want_stat)
     ws_ptr, ws_len = (workspace or _default_ws).get(nbytes, dev)
-    opts = _Opts(int(k_min), int(k_max))
+    opts = _Opts(int(k_min), int(k_max), _PRECISIONS[precision])
     pw = spec._struct()
     _check("score_tracks", load().score_tracks(
         ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, int(top_k),
@@ -301,7 +306,7 @@ class BatchPlan:
     """
 
     def __init__(self, problems: list, K: int, rows_per_step: int = 0, templates_per_lane: int = 0,
-                 workspace=None, stream=None):
+                 precision: str = "plain", workspace=None, stream=None):
         import torch
         self.problems = list(problems)
         self.K = int(K)
@@ -338,7 +343,7 @@ class BatchPlan:
         dev = self.problems[0].coeffs.device if self.problems else torch.device("cuda")
         self._ws = workspace or Workspace()
         ws_ptr, ws_len = self._ws.get(int(nbytes.value), dev)
-        self.opts = _BatchOpts(int(rows_per_step), int(templates_per_lane))
+        self.opts = _BatchOpts(int(rows_per_step), int(templates_per_lane), _PRECISIONS[precision])
         self._plan = _Plan()
         _check("score_batched_plan", lib.score_batched_plan(arr, len(self.problems), self.K, ctypes.byref(self.opts),
                                                             ws_ptr, ws_len, ctypes.byref(self._plan),

@@ -13,7 +13,7 @@ namespace {
 constexpr size_t kLdsLimit = 163840;      // bytes of LDS a gfx950 workgroup may use
 
 struct Layout {
-  size_t seg_off, bound_off, stat_off, topk_off, total;
+  size_t seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off, total;
   int seg_stride;
 };
 
@@ -37,6 +37,12 @@ int make_layout(const emri_power *pw, int K, int64_t n_tmpl, int top_k, bool sta
   off += round_up((size_t)(pw->n_seg > 0 ? pw->n_seg : 1) * L->seg_stride * sizeof(double), 256);
   L->bound_off = off;
   off += round_up((EMRI_MAX_K + 1) * sizeof(double), 256);
+  // tables of the mixed-precision form (sized for its largest K)
+  const size_t n4 = (size_t)((pw->n_seg + 3) & ~3);
+  L->mtab_off = off;
+  off += round_up((n4 > 0 ? n4 : 4) * mixed_row_bytes(MIXED_MAX_K), 256);
+  L->mseg_off = off;
+  off += round_up((n4 > 0 ? n4 : 4) * sizeof(MixedSeg), 256);
   L->stat_off = off;
   if (stat_in_ws) off += round_up((size_t)n_tmpl * sizeof(float), 256);
   L->topk_off = off;
@@ -76,13 +82,21 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   clear_error();
   int st = check_sizes(power, K, n_tmpl, top_k);
   if (st) return st;
-  int k_min = 0, k_max = power->n_bins - 1;
+  int k_min = 0, k_max = power->n_bins - 1, precision = EMRI_PLAIN;
   if (opts) {
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
       if (opts->reserved[i] != 0) return fail(EMRI_EINVAL, "score_opts.reserved must be zero");
     k_min = opts->k_min;
     if (opts->k_max >= 0) k_max = opts->k_max;
+    precision = opts->precision;
   }
+  if (precision != EMRI_PLAIN && precision != EMRI_MIXED)
+    return fail(EMRI_EINVAL, "unknown precision %d", precision);
+  const bool mixed = precision == EMRI_MIXED;
+  if (mixed && (K < 1 || K > MIXED_MAX_K))
+    return fail(EMRI_EUNSUPPORTED, "the mixed-precision form is built for 1 <= K <= %d, not %d", MIXED_MAX_K, K);
+  if (mixed && (bins || n_near_tie))
+    return fail(EMRI_EUNSUPPORTED, "bins and n_near_tie come from the plain validation kernel only");
   if (k_min < 0 || k_max > power->n_bins - 1 || k_min > k_max)
     return fail(EMRI_EINVAL, "bin range [%d, %d] not inside [0, %d]", k_min, k_max, power->n_bins - 1);
   if (power->n_seg > 0 && !power->data) return fail(EMRI_EINVAL, "power->data is NULL");
@@ -102,8 +116,20 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
 
   // LDS staging geometry: two halves of G consecutive rows (see score_internal.h)
   Staging sg;
-  if (!make_staging(power->n_bins, power->row_pitch, elem_bytes(power->dtype), k_min, k_max, 0, kLdsLimit, &sg))
+  const int n4 = (power->n_seg + 3) & ~3;
+  const int mtab_bytes = mixed ? n4 * mixed_row_bytes(K) : 0;
+  const size_t mtab_lds = round_up((size_t)mtab_bytes, 1024);
+  if (mixed) {
+    // four rows per step (one round of matrix products) after the piece table
+    if (!make_staging(power->n_bins, power->row_pitch, elem_bytes(power->dtype), k_min, k_max, 4,
+                      kLdsLimit - mtab_lds, &sg))
+      return fail(EMRI_EUNSUPPORTED,
+                  "the mixed-precision form needs four padded rows of %d bins and the piece table in LDS",
+                  power->n_bins);
+  } else if (!make_staging(power->n_bins, power->row_pitch, elem_bytes(power->dtype), k_min, k_max, 0, kLdsLimit,
+                           &sg)) {
     return fail(EMRI_EUNSUPPORTED, "a spectrogram row of %d bins does not fit twice in LDS", power->n_bins);
+  }
   int cus = 0;
   if ((st = device_cu_count(&cus)) != EMRI_OK) return st;
 
@@ -126,6 +152,10 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     job.K = K;
     job.n_seg = power->n_seg;
     job.seg_stride = L.seg_stride;
+    if (mixed) {
+      job.mtab = ws + L.mtab_off;
+      job.mseg = ws + L.mseg_off;
+    }
     err = launch_score_prep(job, stream);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score prep launch: %s", hipGetErrorString(err));
   }
@@ -147,10 +177,17 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     p.G = sg.G;
     p.half_bytes = sg.half_bytes;
     p.slot_owner = sg.slot_owner;
+    if (mixed) {
+      p.mtab = ws + L.mtab_off;
+      p.mseg = ws + L.mseg_off;
+      p.mtab_bytes = mtab_bytes;
+    }
     const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;
     const int grid = (int)(units < cus ? units : cus);
     p.per_block = (n_tmpl + grid - 1) / grid;
-    if (power->n_seg == 0) {
+    if (mixed && power->n_seg > 0) {
+      err = launch_score_mixed(p, K, power->dtype, grid, mtab_lds + sg.lds, stream);
+    } else if (power->n_seg == 0) {
       // no segment contributes: every statistic is zero; reuse the validation
       // kernel, whose segment loop is then empty
       err = launch_score(p, K, power->dtype, true, grid, sg.lds, stream);

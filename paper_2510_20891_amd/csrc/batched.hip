@@ -65,7 +65,7 @@ int check_problem(const emri_problem &pb, int i, int K, int dtype) {
 // Workspace layout of a batch.
 struct Layout {
   size_t params, prep, topk_jobs, items, block_items, seg, bound, stat, topk, total;
-  std::vector<size_t> seg_off, bound_off, stat_off, topk_off;
+  std::vector<size_t> seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off;
 };
 
 int seg_stride_of(int K) { return (K + 2) & ~1; }
@@ -88,6 +88,9 @@ Layout make_layout(const emri_problem *pbs, int n, int K, int max_items, int gri
     const int ns = pbs[i].power.n_seg > 0 ? pbs[i].power.n_seg : 1;
     L.seg_off.push_back(take(sizeof(double) * ns * seg_stride_of(K)));
     L.bound_off.push_back(take(sizeof(double) * (EMRI_MAX_K + 1)));
+    const size_t n4 = (size_t)((ns + 3) & ~3);
+    L.mtab_off.push_back(take(n4 * mixed_row_bytes(MIXED_MAX_K)));
+    L.mseg_off.push_back(take(n4 * sizeof(MixedSeg)));
     L.stat_off.push_back(pbs[i].stat ? 0 : take(sizeof(float) * pbs[i].n_tmpl));
     L.topk_off.push_back(pbs[i].top_k > 0 ? take(topk_workspace_bytes(pbs[i].top_k)) : 0);
   }
@@ -157,9 +160,18 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   batch_opts o{};
   if (opts) {
     o = *opts;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
       if (o.reserved[i] != 0) return fail(EMRI_EINVAL, "batch_opts.reserved must be zero");
   }
+  if (o.precision != EMRI_PLAIN && o.precision != EMRI_MIXED)
+    return fail(EMRI_EINVAL, "unknown precision %d", o.precision);
+  const bool mixed = o.precision == EMRI_MIXED;
+  if (mixed && (K < 1 || K > MIXED_MAX_K))
+    return fail(EMRI_EUNSUPPORTED, "the mixed-precision form is built for 1 <= K <= %d, not %d", MIXED_MAX_K, K);
+  if (mixed && o.rows_per_step != 0 && o.rows_per_step != 4)
+    return fail(EMRI_EUNSUPPORTED, "the mixed-precision form stages 4 rows per step");
+  if (mixed && o.templates_per_lane != 0 && o.templates_per_lane != mixed_templates_per_lane(K))
+    return fail(EMRI_EUNSUPPORTED, "templates_per_lane %d is not compiled for the mixed form", o.templates_per_lane);
   if (o.rows_per_step != 0 && o.rows_per_step != 1 && o.rows_per_step != 2 && o.rows_per_step != 4)
     return fail(EMRI_EINVAL, "rows_per_step must be 0, 1, 2 or 4");
   const int dtype = n_problems > 0 ? problems[0].power.dtype : EMRI_F32;
@@ -167,8 +179,11 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     const int st = check_problem(problems[i], i, K, dtype);
     if (st) return st;
   }
-  int tpl = 0, st = resolve_tpl(K, o.templates_per_lane, &tpl);
-  if (st) return st;
+  int tpl = 0, st = EMRI_OK;
+  if (mixed)
+    tpl = mixed_templates_per_lane(K);
+  else if ((st = resolve_tpl(K, o.templates_per_lane, &tpl)) != EMRI_OK)
+    return st;
 
   // staging geometry per problem (the requested rows per step, or the most
   // that fit); the launch takes the largest LDS footprint
@@ -177,11 +192,12 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   for (int i = 0; i < n_problems; ++i) {
     const emri_power &pw = problems[i].power;
     const int k_max = problems[i].k_max < 0 ? pw.n_bins - 1 : problems[i].k_max;
-    if (!make_staging(pw.n_bins, pw.row_pitch, elem_bytes(pw.dtype), problems[i].k_min, k_max, o.rows_per_step,
-                      kLdsLimit, &stg[i]))
+    const size_t mtab_lds = mixed ? round_up((size_t)((pw.n_seg + 3) & ~3) * mixed_row_bytes(K), 1024) : 0;
+    if (!make_staging(pw.n_bins, pw.row_pitch, elem_bytes(pw.dtype), problems[i].k_min, k_max,
+                      mixed ? 4 : o.rows_per_step, kLdsLimit - mtab_lds, &stg[i]))
       return fail(EMRI_EUNSUPPORTED, "problem %d: %d rows per step of %d bins do not fit in LDS", i,
-                  o.rows_per_step ? o.rows_per_step : 1, pw.n_bins);
-    lds = std::max(lds, stg[i].lds);
+                  mixed ? 4 : (o.rows_per_step ? o.rows_per_step : 1), pw.n_bins);
+    lds = std::max(lds, mtab_lds + stg[i].lds);
   }
   int cus = 0;
   if ((st = batch_grid(&cus)) != EMRI_OK) return st;
@@ -216,6 +232,11 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     p.G = stg[i].G;
     p.half_bytes = stg[i].half_bytes;
     p.slot_owner = stg[i].slot_owner;
+    if (mixed) {
+      p.mtab = ws + L.mtab_off[i];
+      p.mseg = ws + L.mseg_off[i];
+      p.mtab_bytes = ((pb.power.n_seg + 3) & ~3) * mixed_row_bytes(K);
+    }
     PrepJob &pj = preps[i];
     std::memset(&pj, 0, sizeof pj);
     pj.f0 = pb.f0;
@@ -226,6 +247,10 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     pj.K = K;
     pj.n_seg = pb.power.n_seg;
     pj.seg_stride = seg_stride_of(K);
+    if (mixed) {
+      pj.mtab = ws + L.mtab_off[i];
+      pj.mseg = ws + L.mseg_off[i];
+    }
     if (pb.top_k > 0) {
       topks.push_back(make_topk_job(p.stat, pb.n_tmpl, pb.top_k, pb.topk_val, pb.topk_idx, ws + L.topk_off[i]));
       max_topk_n = std::max(max_topk_n, pb.n_tmpl);
@@ -302,6 +327,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.launch.dtype = dtype;
   pd.launch.tpl = tpl;
   pd.launch.lds = lds;
+  pd.launch.mixed = mixed ? 1 : 0;
   pd.prep_jobs = reinterpret_cast<const PrepJob *>(ws + L.prep);
   pd.topk_jobs = reinterpret_cast<const TopkJob *>(ws + L.topk_jobs);
   pd.n_items = (int)items.size();
@@ -319,7 +345,8 @@ extern "C" int score_batched_run(const emri_batch_plan *plan, void *hip_stream) 
   if (pd.magic != kPlanMagic) return fail(EMRI_EINVAL, "plan was not made by score_batched_plan");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t err = launch_score_prep_batched(pd.prep_jobs, pd.n_problems, stream);
-  if (err == hipSuccess && pd.has_work) err = launch_score_batched(pd.launch, stream);
+  if (err == hipSuccess && pd.has_work)
+    err = pd.launch.mixed ? launch_score_mixed_batched(pd.launch, stream) : launch_score_batched(pd.launch, stream);
   if (err == hipSuccess && pd.n_topk > 0) {
     TopkJobs J;
     std::memset(&J, 0, sizeof J);

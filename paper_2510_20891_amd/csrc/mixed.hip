@@ -1,0 +1,312 @@
+// Mixed-precision form of the scoring kernel: the track contraction
+// sum_k c_k (U T)[alpha, k] of Eq. (10) runs on the matrix cores in BF16 with
+// FP32 accumulation; the per-segment offset f0 T and the rounding to a bin
+// stay in FP64; the power may be stored in FP16.
+//
+// Split products.  Every FP32 coefficient is the exact sum of three BF16
+// pieces c = c0 + c1 + c2 (8 + 8 + 8 significant bits), and every FP64 value
+// U T is split the same way into u0 + u1 + u2 (about 24 bits).  The products
+// kept are those with piece orders a + b <= 2:
+//     c0 u0 + (c0 u1 + c1 u0) + (c0 u2 + c1 u1 + c2 u0),
+// six products per coefficient; the dropped ones are below 2^-24 of |c u|, the
+// size of the FP32 accumulator's own rounding.  They are accumulated smallest
+// first, on top of the fraction phi of f0 T.
+//
+// Layout on the matrix cores (v_mfma_f32_4x4x4_16b_bf16: 16 blocks of a 4x4x4
+// product per wave).  One instruction multiplies the 4 x 4 matrix A (rows = the
+// 4 segments of a staging step, columns = 4 coefficients' pieces) by the 4 x 4
+// matrix B (4 coefficients' pieces of the block's 4 templates); all 16 blocks
+// share A.  Lane l supplies row l%4 of A (segment l%4) and column l%4 of its
+// block's B (its own template), and receives that template's 4 segment
+// results, one per register: register r holds segment r of the step for every
+// lane, so the gathers of one register read one spectrogram row.
+//
+// Per (template, segment), with D the FP32 contraction plus phi:
+//     y = (double)D + (I + 1.5*2^52 + B/E)       (I = rint(f0 T), FP64, exact)
+//     bin address = med3(low word of y, range) * E
+// exactly as in the plain kernel, the FP64 rounding making rint(I + D).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "score_internal.h"
+#include "staging.h"
+
+namespace emri {
+namespace {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kPairs = 6;
+// (U piece, c piece) of the six product groups, smallest first
+constexpr int pair_u(int p) { return p == 0 ? 2 : (p == 1 ? 1 : (p == 2 ? 0 : (p == 3 ? 1 : 0))); }
+constexpr int pair_c(int p) { return p == 0 ? 0 : (p == 1 ? 1 : (p == 2 ? 2 : (p == 3 ? 0 : (p == 4 ? 1 : 0)))); }
+
+__device__ __forceinline__ short4_t pack4(unsigned short a, unsigned short b, unsigned short c, unsigned short d) {
+  short4_t v;
+  v[0] = (short)a;
+  v[1] = (short)b;
+  v[2] = (short)c;
+  v[3] = (short)d;
+  return v;
+}
+
+// The three BF16 pieces of TPL templates' coefficients, KG groups of 4 each.
+template <int KG, int TPL>
+struct Pieces {
+  short4_t v[TPL][3][KG];
+};
+
+// Load and split the coefficients of this lane's TPL templates of tile t0.
+// Returns true if any of them could place a track outside |x| < 2^25 bins
+// (huge or non-finite values), from the per-segment bound of prep.
+template <int K, int KG, int TPL>
+__device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, int64_t j_end, Pieces<KG, TPL> &pc) {
+  const int tid = threadIdx.x;
+  typedef const __attribute__((address_space(4))) double *const_dptr;
+  const_dptr bnd = (const_dptr)p.bound;
+  bool wild = false;
+#pragma unroll
+  for (int s = 0; s < TPL; ++s) {
+    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+    const bool live = j < j_end;
+    float cf[4 * KG];
+#pragma unroll
+    for (int k = 0; k < 4 * KG; ++k) cf[k] = 0.0f;
+    if constexpr (K % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < K; k += 4) {
+        const float4 v = live ? reinterpret_cast<const float4 *>(p.coeffs + (size_t)j * K)[k / 4]
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        cf[k] = v.x;
+        cf[k + 1] = v.y;
+        cf[k + 2] = v.z;
+        cf[k + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
+    }
+    double b = bnd[0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) b += __builtin_fabs((double)cf[k]) * bnd[1 + k];
+    wild |= !(b < 0.25 * kWildLimit);
+#pragma unroll
+    for (int g = 0; g < KG; ++g) {
+      unsigned short h[3][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float c = cf[4 * g + q];
+        h[0][q] = bf16_rne(c);
+        const float r1 = c - bf16_value(h[0][q]);       // exact
+        h[1][q] = bf16_rne(r1);
+        const float r2 = r1 - bf16_value(h[1][q]);      // exact; at most 8 significant bits
+        h[2][q] = bf16_rne(r2);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) pc.v[s][a][g] = pack4(h[a][0], h[a][1], h[a][2], h[a][3]);
+    }
+  }
+  return wild;
+}
+
+// One tile: TPL slots of 512 templates against every segment, 4 segments
+// (one staging step) per round of matrix products.
+template <int KG, int TPL, typename PT, bool WILD>
+__device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, unsigned char *tab, unsigned char *lds,
+                                               const Pieces<KG, TPL> &pc, double (&sum)[TPL]) {
+  constexpr int E = Elem<PT>::bytes;
+  float acc[TPL];
+#pragma unroll
+  for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
+  const Pipe pp = pipe_init<PT>(p);
+  const int lane = (int)(threadIdx.x & 63);
+  const MixedSeg *ms = reinterpret_cast<const MixedSeg *>(p.mseg);
+  pipe_issue(p, pp, lds, 0, 0);
+  pipe_publish<PT>(p, pp, lds, 0);
+  int half = 0;
+  for (int r0 = 0; r0 < p.n_seg; r0 += 4) {
+    pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
+    // A operands: this lane's row is segment r0 + lane % 4
+    short4_t ua[3][KG];
+    {
+      const short4_t *row = reinterpret_cast<const short4_t *>(tab + (size_t)(r0 + (lane & 3)) * (3 * KG * 8));
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < KG; ++g) ua[a][g] = row[a * KG + g];
+    }
+    const MixedSeg m0 = load_uniform(ms + r0), m1 = load_uniform(ms + r0 + 1), m2 = load_uniform(ms + r0 + 2),
+                   m3 = load_uniform(ms + r0 + 3);
+    float4_t d[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      d[s][0] = m0.phi;
+      d[s][1] = m1.phi;
+      d[s][2] = m2.phi;
+      d[s][3] = m3.phi;
+    }
+#pragma unroll
+    for (int q = 0; q < kPairs; ++q)
+#pragma unroll
+      for (int g = 0; g < KG; ++g)
+#pragma unroll
+        for (int s = 0; s < TPL; ++s)
+          d[s] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ua[pair_u(q)][g], pc.v[s][pair_c(q)][g], d[s], 0, 0, 0);
+    const double Is[4] = {m0.I, m1.I, m2.I, m3.I};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int seg = r0 + r;
+      if (seg >= p.n_seg) break;
+      const BufConst bc = buffer_consts<PT>(p, lds, half, r);
+      const double shift = Is[r] + bc.magic;       // I + 1.5*2^52 + base: exact
+      float v[TPL];
+#pragma unroll
+      for (int s = 0; s < TPL; ++s) {
+        double y;
+        if constexpr (WILD) {
+          const double x = (double)d[s][r] + Is[r];
+          y = (__builtin_fabs(x) < kWildLimit) ? x + bc.magic : bc.magic - 2.0;
+        } else {
+          y = (double)d[s][r] + shift;
+        }
+        v[s] = Elem<PT>::load(E * clamp_i32(low_word(y), bc.lo, bc.hi));
+      }
+#pragma unroll
+      for (int s = 0; s < TPL; ++s) acc[s] += v[s];
+      if ((seg & 7) == 7 || seg + 1 == p.n_seg) {
+#pragma unroll
+        for (int s = 0; s < TPL; ++s) {
+          sum[s] += (double)acc[s];
+          acc[s] = 0.0f;
+        }
+      }
+    }
+    pipe_publish<PT>(p, pp, lds, half ^ 1);
+    half ^= 1;
+  }
+}
+
+// Copy the piece table of a stream into the front of LDS (before the staging halves).
+__device__ __forceinline__ void load_table(const ScoreParams &p, unsigned char *tab) {
+  const int n16 = p.mtab_bytes >> 4;
+  const uint4 *src = reinterpret_cast<const uint4 *>(p.mtab);
+  uint4 *dst = reinterpret_cast<uint4 *>(tab);
+  for (int i = threadIdx.x; i < n16; i += SCORE_THREADS) dst[i] = src[i];
+}
+
+__device__ __forceinline__ unsigned char *staging_base(const ScoreParams &p, unsigned char *lds) {
+  return lds + ((p.mtab_bytes + 1023) & ~1023);
+}
+
+template <int K, int TPL, typename PT>
+__device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
+                                                  int64_t j_end) {
+  constexpr int KG = (K + 3) / 4;
+  unsigned char *stage = staging_base(p, lds);
+  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * SCORE_THREADS) {
+    Pieces<KG, TPL> pc;
+    const bool wild = load_pieces<K, KG, TPL>(p, t0, j_end, pc);
+    double sum[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) sum[s] = 0.0;
+    if (__any(wild))
+      run_tile_mixed<KG, TPL, PT, true>(p, lds, stage, pc, sum);
+    else
+      run_tile_mixed<KG, TPL, PT, false>(p, lds, stage, pc, sum);
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + threadIdx.x;
+      if (j < j_end) p.stat[j] = (float)sum[s];
+    }
+  }
+}
+
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_mixed_kernel(ScoreParams p) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  load_table(p, lds);
+  init_lds(p, staging_base(p, lds));
+  const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
+  const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
+  score_range_mixed<K, TPL, PT>(p, lds, j_begin, j_end);
+}
+
+// Batched form of the mixed kernel (same work items as the plain batched kernel).
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(SCORE_THREADS) void score_mixed_batched_kernel(const ScoreParams *__restrict__ params,
+                                                                            const BatchItem *__restrict__ items,
+                                                                            const int *__restrict__ block_items) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  typedef const __attribute__((address_space(4))) int *const_ints;
+  const int first = ((const_ints)block_items)[blockIdx.x];
+  const int last = ((const_ints)block_items)[blockIdx.x + 1];
+  for (int it = first; it < last; ++it) {
+    const BatchItem item = load_uniform(items + it);
+    const ScoreParams p = load_uniform(params + item.stream);
+    __syncthreads();              // the previous item's last reads of the table are done
+    load_table(p, lds);
+    init_lds(p, staging_base(p, lds));
+    score_range_mixed<K, TPL, PT>(p, lds, item.begin, item.end);
+  }
+}
+
+constexpr int mixed_tpl(int K) { return K <= 4 ? 10 : (K <= 8 ? 8 : (K <= 12 ? 6 : 5)); }
+
+template <typename Kern>
+hipError_t set_lds(Kern kern, size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <int K, typename PT>
+hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
+  auto kern = score_mixed_kernel<K, mixed_tpl(K), PT>;
+  hipError_t err = set_lds(kern, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p);
+  return hipGetLastError();
+}
+
+template <int K, typename PT>
+hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
+  auto kern = score_mixed_batched_kernel<K, mixed_tpl(K), PT>;
+  hipError_t err = set_lds(kern, b.lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
+  return hipGetLastError();
+}
+
+template <typename PT, int... Ks>
+hipError_t dispatch_mixed(int K, const ScoreParams &p, int grid, size_t lds, hipStream_t stream,
+                          std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  ((K == Ks + 1 ? (err = launch_mixed_k<Ks + 1, PT>(p, grid, lds, stream), true) : false) || ...);
+  return err;
+}
+
+template <typename PT, int... Ks>
+hipError_t dispatch_mixed_batched(int K, const BatchLaunch &b, hipStream_t stream, std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  ((K == Ks + 1 ? (err = launch_mixed_batched_k<Ks + 1, PT>(b, stream), true) : false) || ...);
+  return err;
+}
+
+}  // namespace
+
+int mixed_templates_per_lane(int K) { return mixed_tpl(K); }
+
+hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream) {
+  using Ks = std::make_integer_sequence<int, MIXED_MAX_K>;
+  if (dtype == EMRI_F32) return dispatch_mixed<float>(K, p, grid, lds, stream, Ks{});
+  return dispatch_mixed<__half>(K, p, grid, lds, stream, Ks{});
+}
+
+hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream) {
+  using Ks = std::make_integer_sequence<int, MIXED_MAX_K>;
+  if (b.dtype == EMRI_F32) return dispatch_mixed_batched<float>(b.K, b, stream, Ks{});
+  return dispatch_mixed_batched<__half>(b.K, b, stream, Ks{});
+}
+
+}  // namespace emri

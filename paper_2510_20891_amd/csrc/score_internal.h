@@ -31,7 +31,25 @@ struct ScoreParams {
   int G;                      // rows per staging step (1, 2 or 4)
   int half_bytes;             // bytes of one LDS half: lead-in + G rows rounded up to 1 KB
   uint32_t slot_owner;        // nibble j: wave that re-zeroes zero slot j after a copy (>= 8: none)
+  // mixed-precision form only (null otherwise)
+  const void *mtab;           // per segment: 3 BF16 pieces of U*T, MIXED_GROUPS(K) groups of 4 k
+  const void *mseg;           // per segment: MixedSeg
+  int mtab_bytes;             // bytes of mtab for round_up(n_seg, 4) segments (staged in LDS first)
+  int pad_;
 };
+
+// Mixed-precision form: per-segment offset f0*T = I + phi with I = rint(f0*T)
+// (FP64, an integer) and phi in [-1/2, 1/2] (FP32).
+struct MixedSeg {
+  double I;
+  float phi;
+  float pad;
+};
+
+constexpr int MIXED_MAX_K = 16;
+__host__ __device__ constexpr int mixed_groups(int K) { return (K + 3) / 4; }
+// bytes of the BF16 piece table per segment: 3 pieces x groups x 4 values x 2 bytes
+__host__ __device__ constexpr int mixed_row_bytes(int K) { return 3 * mixed_groups(K) * 8; }
 
 // LDS staging of spectrogram rows.  Two halves, each a 16-byte lead-in followed
 // by G consecutive rows exactly as they lie in HBM (pitch_bytes apart), copied
@@ -63,6 +81,8 @@ struct PrepJob {
   unsigned long long *near_tie;
   double t_sft;
   int K, n_seg, seg_stride, pad;
+  void *mtab;                  // mixed-precision tables, or null
+  void *mseg;
 };
 
 // Launch shape of a batched scoring launch (device tables live in the workspace).
@@ -72,6 +92,7 @@ struct BatchLaunch {
   const int *block_items;
   int grid, K, dtype, tpl;
   size_t lds;
+  int mixed, pad;
 };
 
 // Read a small trivially copyable struct from read-only device memory with
@@ -94,6 +115,10 @@ hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, hipStream_
 hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, int grid, size_t lds,
                         hipStream_t stream);
 hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream);
+// mixed-precision form (BF16-split MFMA contraction, FP64 offset and rounding)
+int mixed_templates_per_lane(int K);
+hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream);
+hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream);
 
 struct TopkState {
   uint32_t key_prefix;        // bits of the k-th largest key found so far

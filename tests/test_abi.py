@@ -193,3 +193,31 @@ def test_batched_workspace_size_and_validation():
 def test_batched_tile_options():
     assert emri.batched_tile_options(8)[0] == 9 and len(emri.batched_tile_options(8)) == 2
     assert len(emri.batched_tile_options(5)) == 1
+
+
+def test_mixed_precision_validation():
+    lib = emri.load()
+    nb = ctypes.c_size_t()
+    pw = _power()
+    assert lib.score_tracks_workspace_size(ctypes.byref(pw), 8, 10, 2, 0, ctypes.byref(nb)) == 0
+    ws = 0x100000
+
+    def call(K=8, precision=1, pitch=40, bins=None, reserved=0):
+        p = _power(pitch=pitch)
+        o = emri._Opts(0, -1, precision)
+        o.reserved[0] = reserved
+        return lib.score_tracks(ctypes.byref(p), FAKE, FAKE, K, FAKE, 10, 2, FAKE, FAKE, FAKE, bins, None,
+                                ctypes.byref(o), ws, 1 << 30, None)
+    assert call(K=0) == -5 and call(K=17) == -5          # built for 1 <= K <= 16
+    assert call(precision=2) == -1                       # unknown precision
+    assert call(bins=FAKE) == -5                         # no validation kernel for the mixed form
+    assert call(reserved=1) == -1
+    assert call(pitch=33) == -1                          # pitch not a multiple of 8
+    opts = emri._BatchOpts(0, 0, 1)
+    plan = emri._Plan()
+    arr = (emri._Problem * 1)(_problem())
+    assert lib.score_batched_plan(arr, 1, 17, ctypes.byref(opts), FAKE, 1 << 30, ctypes.byref(plan), None) == -5
+    assert lib.score_batched_plan(arr, 1, 8, ctypes.byref(emri._BatchOpts(2, 0, 1)), FAKE, 1 << 30,
+                                  ctypes.byref(plan), None) == -5      # four rows per step only
+    assert lib.score_batched_plan(arr, 1, 8, ctypes.byref(emri._BatchOpts(0, 0, 3)), FAKE, 1 << 30,
+                                  ctypes.byref(plan), None) == -1
