@@ -177,6 +177,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
     p.G = sg.G;
     p.half_bytes = sg.half_bytes;
     p.slot_owner = sg.slot_owner;
+    p.one = 1.0f;
     if (mixed) {
       p.mtab = ws + L.mtab_off;
       p.mseg = ws + L.mseg_off;

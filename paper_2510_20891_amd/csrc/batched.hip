@@ -232,6 +232,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     p.G = stg[i].G;
     p.half_bytes = stg[i].half_bytes;
     p.slot_owner = stg[i].slot_owner;
+    p.one = 1.0f;
     if (mixed) {
       p.mtab = ws + L.mtab_off[i];
       p.mseg = ws + L.mseg_off[i];

@@ -155,13 +155,15 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, unsigned ch
         for (int s = 0; s < TPL; ++s)
           d[s] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ua[pair_u(q)][g], pc.v[s][pair_c(q)][g], d[s], 0, 0, 0);
     const double Is[4] = {m0.I, m1.I, m2.I, m3.I};
+    // Bins of the 4 segments, software pipelined: the gathers of segment r are
+    // in flight while the addresses of segment r+1 are computed.  Segments
+    // past n_seg (last step) gather in-bounds stale data that is not added.
+    typename Elem<PT>::raw_t v[TPL];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int seg = r0 + r;
-      if (seg >= p.n_seg) break;
       const BufConst bc = buffer_consts<PT>(p, lds, half, r);
       const double shift = Is[r] + bc.magic;       // I + 1.5*2^52 + base: exact
-      float v[TPL];
+      int addr[TPL];
 #pragma unroll
       for (int s = 0; s < TPL; ++s) {
         double y;
@@ -171,16 +173,32 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, unsigned ch
         } else {
           y = (double)d[s][r] + shift;
         }
-        v[s] = Elem<PT>::load(E * clamp_i32(low_word(y), bc.lo, bc.hi));
+        addr[s] = E * clamp_i32(low_word(y), bc.lo, bc.hi);
+      }
+      if (r > 0) {
+        __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): gathers of segment r-1
+        __builtin_amdgcn_sched_barrier(0);
+        if (r0 + r - 1 < p.n_seg) {
+#pragma unroll
+          for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+        }
       }
 #pragma unroll
-      for (int s = 0; s < TPL; ++s) acc[s] += v[s];
-      if ((seg & 7) == 7 || seg + 1 == p.n_seg) {
+      for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::raw(addr[s]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+    if (r0 + 3 < p.n_seg) {
 #pragma unroll
-        for (int s = 0; s < TPL; ++s) {
-          sum[s] += (double)acc[s];
-          acc[s] = 0.0f;
-        }
+      for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+    }
+    // FP32 runs of 8 segments (two steps), then FP64, as in the plain kernel
+    if ((r0 & 4) != 0 || r0 + 4 >= p.n_seg) {
+#pragma unroll
+      for (int s = 0; s < TPL; ++s) {
+        sum[s] += (double)acc[s];
+        acc[s] = 0.0f;
       }
     }
     pipe_publish<PT>(p, pp, lds, half ^ 1);

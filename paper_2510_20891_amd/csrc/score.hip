@@ -99,9 +99,9 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
     for (int i = 0; i < G; ++i) {
       const int r = r0 + i;
       if (r >= p.n_seg) break;
-      float v[TPL];
+      typename Elem<PT>::raw_t v[TPL];
 #pragma unroll
-      for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::load(E * addr[s]);
+      for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::raw(E * addr[s]);
       // Bins of segment r+1 (for the last segment this computes clamped, unused
       // addresses), then the constants of segment r+2, issued after the FMAs so
       // that the wait for this segment's gathers also covers them.
@@ -114,7 +114,7 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
       __builtin_amdgcn_s_waitcnt(0xC07F);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int s = 0; s < TPL; ++s) acc[s] += v[s];
+      for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
       if ((r & 7) == 7 || r + 1 == p.n_seg) {
 #pragma unroll
         for (int s = 0; s < TPL; ++s) {
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
         const BufConst bc = buffer_consts<PT>(p, lds, half, i);
         const int word = low_word(ys + bc.magic);
         const int b = word - bc.base;
-        acc += Elem<PT>::load(E * clamp_i32(word, bc.lo, bc.hi));
+        acc = Elem<PT>::add(acc, Elem<PT>::raw(E * clamp_i32(word, bc.lo, bc.hi)), p.one);
         if (live && p.bins) p.bins[(size_t)j * p.n_seg + a] = (b >= p.k_min && b <= p.k_max) ? b : -1;
         if ((a & 7) == 7 || a + 1 == p.n_seg) {
           sum += (double)acc;

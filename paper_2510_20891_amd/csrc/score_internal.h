@@ -35,7 +35,7 @@ struct ScoreParams {
   const void *mtab;           // per segment: 3 BF16 pieces of U*T, MIXED_GROUPS(K) groups of 4 k
   const void *mseg;           // per segment: MixedSeg
   int mtab_bytes;             // bytes of mtab for round_up(n_seg, 4) segments (staged in LDS first)
-  int pad_;
+  float one;                  // 1.0f: FP16 power is added as fma(P, one, acc), one instruction
 };
 
 // Mixed-precision form: per-segment offset f0*T = I + phi with I = rint(f0*T)

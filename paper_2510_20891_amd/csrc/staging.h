@@ -22,21 +22,29 @@ typedef __attribute__((address_space(3))) unsigned char lds_byte;
 // LDS byte address of a pointer into dynamic shared memory.
 __device__ __forceinline__ int lds_address(const void *p) { return (int)(size_t)(const lds_byte *)p; }
 
+// Power elements in LDS.  raw() is the gathered element as stored; add()
+// widens it into an FP32 accumulator (for FP16 one v_fma_mix_f32: the product
+// with 1.0 is exact, so the result is the rounded sum acc + P).
 template <typename PT>
 struct Elem;
 template <>
 struct Elem<float> {
   static constexpr int bytes = 4;
-  __device__ static float load(int addr) { return *(const __attribute__((address_space(3))) float *)(size_t)addr; }
+  typedef float raw_t;
+  __device__ static float raw(int addr) { return *(const __attribute__((address_space(3))) float *)(size_t)addr; }
+  __device__ static float add(float acc, float v, float) { return acc + v; }
+  __device__ static float load(int addr) { return raw(addr); }
   __device__ static void zero(int addr) { *(__attribute__((address_space(3))) float *)(size_t)addr = 0.0f; }
 };
 template <>
 struct Elem<__half> {
   static constexpr int bytes = 2;
-  __device__ static float load(int addr) {
-    const unsigned short h = *(const __attribute__((address_space(3))) unsigned short *)(size_t)addr;
-    return (float)__builtin_bit_cast(_Float16, h);
+  typedef _Float16 raw_t;
+  __device__ static _Float16 raw(int addr) {
+    return __builtin_bit_cast(_Float16, *(const __attribute__((address_space(3))) unsigned short *)(size_t)addr);
   }
+  __device__ static float add(float acc, _Float16 v, float one) { return __builtin_fmaf((float)v, one, acc); }
+  __device__ static float load(int addr) { return (float)raw(addr); }
   __device__ static void zero(int addr) {
     *(__attribute__((address_space(3))) unsigned short *)(size_t)addr = (unsigned short)0;
   }
