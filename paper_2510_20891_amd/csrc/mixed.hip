@@ -111,98 +111,155 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
   return wild;
 }
 
-// One tile: TPL slots of 512 templates against every segment, 4 segments
-// (one staging step) per round of matrix products.
+// Part PART of 4 of the matrix products of one staging step: instructions
+// [PART*NI/4, (PART+1)*NI/4) of every slot's chain (NI = 6*KG, smallest
+// products first); the chains start from phi.
+template <int KG, int TPL, int PART>
+__device__ __forceinline__ void products_part(const short4_t (&ua)[3][KG], const float4_t &phi,
+                                              const Pieces<KG, TPL> &pc, float4_t (&d)[TPL]) {
+  constexpr int NI = kPairs * KG;
+#pragma unroll
+  for (int i = PART * NI / 4; i < (PART + 1) * NI / 4; ++i)
+#pragma unroll
+    for (int s = 0; s < TPL; ++s)
+      d[s] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ua[pair_u(i / KG)][i % KG], pc.v[s][pair_c(i / KG)][i % KG],
+                                                    i == 0 ? phi : d[s], 0, 0, 0);
+}
+
+template <int KG, int TPL>
+__device__ __forceinline__ void step_products(const short4_t (&ua)[3][KG], const float4_t &phi,
+                                              const Pieces<KG, TPL> &pc, float4_t (&d)[TPL]) {
+  products_part<KG, TPL, 0>(ua, phi, pc, d);
+  products_part<KG, TPL, 1>(ua, phi, pc, d);
+  products_part<KG, TPL, 2>(ua, phi, pc, d);
+  products_part<KG, TPL, 3>(ua, phi, pc, d);
+}
+
+// Operands of step r0: the A rows (segment r0 + lane % 4), the fractions phi
+// of f0 T (the chains' start) and the integer offsets I.
+template <int KG>
+__device__ __forceinline__ void step_operands(const unsigned char *tab, const MixedSeg *ms, int r0, short4_t (&ua)[3][KG],
+                                              float4_t &phi, double (&I)[4]) {
+  const int lane = (int)(threadIdx.x & 63);
+  const short4_t *row = reinterpret_cast<const short4_t *>(tab + (size_t)(r0 + (lane & 3)) * (3 * KG * 8));
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int g = 0; g < KG; ++g) ua[a][g] = row[a * KG + g];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const MixedSeg m = load_uniform(ms + r0 + r);
+    I[r] = m.I;
+    phi[r] = m.phi;
+  }
+}
+
+// Interleave the matrix products just issued with the vector work of the same
+// scheduling region: one product, then two vector instructions, N times.
+template <int N>
+__device__ __forceinline__ void interleave_products() {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);   // two VALU
+  }
+}
+
+// One staging step r0 (4 segments) with the products dc of this step, while
+// the products dn of the next step are issued a quarter per segment,
+// interleaved with the address arithmetic.  The gathers of segment r are in
+// flight while the addresses of segment r+1 are computed.  Segments past
+// n_seg (last step) gather in-bounds stale data that is not added.
+template <int KG, int TPL, typename PT, bool WILD>
+__device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp, const unsigned char *tab,
+                                           unsigned char *lds, const Pieces<KG, TPL> &pc, int r0, int half,
+                                           const float4_t (&dc)[TPL], const double (&Ic)[4], float4_t (&dn)[TPL],
+                                           double (&In)[4], float (&acc)[TPL], double (&sum)[TPL]) {
+  constexpr int E = Elem<PT>::bytes;
+  constexpr int NQ = kPairs * KG / 4 * TPL;       // products per quarter (lower bound)
+  pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
+  const bool more = r0 + 4 < p.n_seg;
+  short4_t ua[3][KG];
+  float4_t phi;
+  step_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), more ? r0 + 4 : r0, ua, phi, In);
+  __builtin_amdgcn_s_waitcnt(0xC07F);          // operands in registers before the interleaved region
+  __builtin_amdgcn_sched_barrier(0);
+  typename Elem<PT>::raw_t v[TPL];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const BufConst bc = buffer_consts<PT>(p, lds, half, r);
+    const double shift = Ic[r] + bc.magic;       // I + 1.5*2^52 + base: exact
+    int addr[TPL];
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      double y;
+      if constexpr (WILD) {
+        const double x = (double)dc[s][r] + Ic[r];
+        y = (__builtin_fabs(x) < kWildLimit) ? x + bc.magic : bc.magic - 2.0;
+      } else {
+        y = (double)dc[s][r] + shift;
+      }
+      addr[s] = E * clamp_i32(low_word(y), bc.lo, bc.hi);
+    }
+    if (r == 0) products_part<KG, TPL, 0>(ua, phi, pc, dn);
+    if (r == 1) products_part<KG, TPL, 1>(ua, phi, pc, dn);
+    if (r == 2) products_part<KG, TPL, 2>(ua, phi, pc, dn);
+    if (r == 3) products_part<KG, TPL, 3>(ua, phi, pc, dn);
+    interleave_products<NQ>();
+    if (r > 0) {
+      __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0): gathers of segment r-1
+      __builtin_amdgcn_sched_barrier(0);
+      if (r0 + r - 1 < p.n_seg) {
+#pragma unroll
+        for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::raw(addr[s]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __builtin_amdgcn_s_waitcnt(0xC07F);
+  __builtin_amdgcn_sched_barrier(0);
+  if (r0 + 3 < p.n_seg) {
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+  }
+  // FP32 runs of 8 segments (two steps), then FP64, as in the plain kernel
+  if ((r0 & 4) != 0 || !more) {
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) {
+      sum[s] += (double)acc[s];
+      acc[s] = 0.0f;
+    }
+  }
+  pipe_publish<PT>(p, pp, lds, half ^ 1);
+}
+
+// One tile: TPL slots of 512 templates against every segment.  Software
+// pipelined: while a wave gathers with the products of step n it also issues
+// the matrix products of step n+1 (two steps per loop turn, so the two product
+// buffers swap roles without copies).
 template <int KG, int TPL, typename PT, bool WILD>
 __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, unsigned char *tab, unsigned char *lds,
                                                const Pieces<KG, TPL> &pc, double (&sum)[TPL]) {
-  constexpr int E = Elem<PT>::bytes;
   float acc[TPL];
 #pragma unroll
   for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
   const Pipe pp = pipe_init<PT>(p);
-  const int lane = (int)(threadIdx.x & 63);
-  const MixedSeg *ms = reinterpret_cast<const MixedSeg *>(p.mseg);
   pipe_issue(p, pp, lds, 0, 0);
   pipe_publish<PT>(p, pp, lds, 0);
-  int half = 0;
-  for (int r0 = 0; r0 < p.n_seg; r0 += 4) {
-    pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
-    // A operands: this lane's row is segment r0 + lane % 4
+  float4_t da[TPL], db[TPL];
+  double Ia[4], Ib[4];
+  if (p.n_seg > 0) {
     short4_t ua[3][KG];
-    {
-      const short4_t *row = reinterpret_cast<const short4_t *>(tab + (size_t)(r0 + (lane & 3)) * (3 * KG * 8));
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int g = 0; g < KG; ++g) ua[a][g] = row[a * KG + g];
-    }
-    const MixedSeg m0 = load_uniform(ms + r0), m1 = load_uniform(ms + r0 + 1), m2 = load_uniform(ms + r0 + 2),
-                   m3 = load_uniform(ms + r0 + 3);
-    float4_t d[TPL];
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) {
-      d[s][0] = m0.phi;
-      d[s][1] = m1.phi;
-      d[s][2] = m2.phi;
-      d[s][3] = m3.phi;
-    }
-#pragma unroll
-    for (int q = 0; q < kPairs; ++q)
-#pragma unroll
-      for (int g = 0; g < KG; ++g)
-#pragma unroll
-        for (int s = 0; s < TPL; ++s)
-          d[s] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ua[pair_u(q)][g], pc.v[s][pair_c(q)][g], d[s], 0, 0, 0);
-    const double Is[4] = {m0.I, m1.I, m2.I, m3.I};
-    // Bins of the 4 segments, software pipelined: the gathers of segment r are
-    // in flight while the addresses of segment r+1 are computed.  Segments
-    // past n_seg (last step) gather in-bounds stale data that is not added.
-    typename Elem<PT>::raw_t v[TPL];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const BufConst bc = buffer_consts<PT>(p, lds, half, r);
-      const double shift = Is[r] + bc.magic;       // I + 1.5*2^52 + base: exact
-      int addr[TPL];
-#pragma unroll
-      for (int s = 0; s < TPL; ++s) {
-        double y;
-        if constexpr (WILD) {
-          const double x = (double)d[s][r] + Is[r];
-          y = (__builtin_fabs(x) < kWildLimit) ? x + bc.magic : bc.magic - 2.0;
-        } else {
-          y = (double)d[s][r] + shift;
-        }
-        addr[s] = E * clamp_i32(low_word(y), bc.lo, bc.hi);
-      }
-      if (r > 0) {
-        __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0): gathers of segment r-1
-        __builtin_amdgcn_sched_barrier(0);
-        if (r0 + r - 1 < p.n_seg) {
-#pragma unroll
-          for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
-        }
-      }
-#pragma unroll
-      for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::raw(addr[s]);
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_sched_barrier(0);
-    if (r0 + 3 < p.n_seg) {
-#pragma unroll
-      for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
-    }
-    // FP32 runs of 8 segments (two steps), then FP64, as in the plain kernel
-    if ((r0 & 4) != 0 || r0 + 4 >= p.n_seg) {
-#pragma unroll
-      for (int s = 0; s < TPL; ++s) {
-        sum[s] += (double)acc[s];
-        acc[s] = 0.0f;
-      }
-    }
-    pipe_publish<PT>(p, pp, lds, half ^ 1);
-    half ^= 1;
+    float4_t phi;
+    step_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), 0, ua, phi, Ia);
+    step_products<KG, TPL>(ua, phi, pc, da);
+  }
+  for (int r0 = 0; r0 < p.n_seg; r0 += 8) {
+    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0, 0, da, Ia, db, Ib, acc, sum);
+    if (r0 + 4 >= p.n_seg) break;
+    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, da, Ia, acc, sum);
   }
 }
 
@@ -270,7 +327,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_mixed_batched_kernel(cons
   }
 }
 
-constexpr int mixed_tpl(int K) { return K <= 4 ? 10 : (K <= 8 ? 8 : (K <= 12 ? 6 : 5)); }
+constexpr int mixed_tpl(int K) { return K <= 4 ? 8 : (K <= 8 ? 6 : (K <= 12 ? 5 : 4)); }
 
 template <typename Kern>
 hipError_t set_lds(Kern kern, size_t lds) {

@@ -460,12 +460,12 @@ bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_ma
   }
   const int half = (int)half_of(G);
   const int copied = half - SCORE_LDS_LEAD;     // bytes a full step writes
-  uint32_t owner = 0xffffffffu;
+  uint64_t owner = ~0ull;
   for (int j = 0; j < 2 * G; ++j) {
     const int bin = (j & 1) ? k_max + 1 : k_min - 1;
     const int rel = (j >> 1) * pitch_bytes + elem_bytes * bin;
-    const uint32_t w = (rel >= 0 && rel < copied) ? (uint32_t)((rel >> 10) % SCORE_WAVES) : 15u;
-    owner = (owner & ~(15u << (4 * j))) | (w << (4 * j));
+    const uint64_t w = (rel >= 0 && rel < copied) ? (uint64_t)((rel >> 10) % SCORE_WAVES) : 0xffull;
+    owner = (owner & ~(0xffull << (8 * j))) | (w << (8 * j));
   }
   out->G = G;
   out->pitch_bytes = pitch_bytes;

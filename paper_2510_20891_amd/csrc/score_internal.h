@@ -30,7 +30,7 @@ struct ScoreParams {
   int pitch_bytes;            // bytes between rows, in HBM and between LDS row buffers
   int G;                      // rows per staging step (1, 2 or 4)
   int half_bytes;             // bytes of one LDS half: lead-in + G rows rounded up to 1 KB
-  uint32_t slot_owner;        // nibble j: wave that re-zeroes zero slot j after a copy (>= 8: none)
+  uint64_t slot_owner;        // byte j: wave that re-zeroes zero slot j after a copy (0xff: none)
   // mixed-precision form only (null otherwise)
   const void *mtab;           // per segment: 3 BF16 pieces of U*T, MIXED_GROUPS(K) groups of 4 k
   const void *mseg;           // per segment: MixedSeg
@@ -57,7 +57,7 @@ __host__ __device__ constexpr int mixed_row_bytes(int K) { return 3 * mixed_grou
 // row buffer j/2: the bin below k_min (j even) or above k_max (j odd).
 struct Staging {
   int G, pitch_bytes, half_bytes;
-  uint32_t slot_owner;
+  uint64_t slot_owner;
   size_t lds;                 // bytes of dynamic LDS (both halves and a 16-byte tail)
 };
 

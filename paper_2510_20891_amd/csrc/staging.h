@@ -107,7 +107,7 @@ __device__ __forceinline__ Pipe pipe_init(const ScoreParams &p) {
   if (lane < 2 * p.G) {
     const int bin = (lane & 1) ? p.k_max + 1 : p.k_min - 1;
     pp.slot_off = kLeadIn + (lane >> 1) * p.pitch_bytes + E * bin;
-    pp.slot_mine = (int)((p.slot_owner >> (4 * lane)) & 15u) == pp.wave;
+    pp.slot_mine = (int)((p.slot_owner >> (8 * lane)) & 0xffu) == pp.wave;
   }
   return pp;
 }
