@@ -31,6 +31,11 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "score_fast_k8_f32_one_year_traffic.json")
 
 _POOL_STATE = {}
@@ -92,6 +97,208 @@ def copy_calibration(nbytes: int) -> int:
     return 0
 
 
+# ----------------------------------------------------------------------------- forms
+def _event_ms(fn, reps: int, stream=None) -> float:
+    """Median wall time of fn() on the current stream, by HIP events, over reps runs."""
+    import statistics
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return statistics.median(out)
+
+
+def precision_form(st, reps: int = 5) -> dict:
+    """Config 2: the one-year stream, 1e8 templates at K = 8 and K = 16, top-100.
+    Plain FP32 (the plain path) vs plain FP16 vs mixed FP16; statistic error of
+    the mixed form against the FP64 oracle on 2e5 sampled templates; top-100
+    overlap against the oracle's exact top-100 (the oracle scores the union of
+    the plain and mixed top-2000, which holds the true top-100 because the
+    plain statistic is within 1e-5 of the oracle's)."""
+    import torch
+    import oracle
+    import paper_2510_20891_amd as emri
+    dev = torch.device("cuda:0")
+    n, top_k = 100_000_000, 100
+    x_d = torch.from_numpy(st["x"]).to(dev)
+    psd_d = torch.from_numpy(st["psd"]).to(dev)
+    spec32 = emri.build_sfts(x_d, st["dt"], st["n_sft"], psd_d, dtype="f32")
+    spec16 = emri.build_sfts(x_d, st["dt"], st["n_sft"], psd_d, dtype="f16")
+    P16 = spec16.power().cpu().numpy().astype(np.float64)
+    t_sft = spec16.t_sft
+    res = {"workload": "one-year stream (192 x 8193), 1e8 templates uniform in the K-basis box, top-100",
+           "power": "f16 for mixed and plain_f16, f32 for plain_f32"}
+    ws = emri.Workspace()
+    for K in (8, 16):
+        f0, U, sv, lo, hi = emri.build_basis(st["tracks"], K)
+        f0_d, U_d = torch.from_numpy(f0).to(dev), torch.from_numpy(U).to(dev)
+        C_d = synth.device_coefficients(2, K, n, lo, hi, dev)
+        out = {"stat": torch.empty(n, dtype=torch.float32, device=dev),
+               "topk_val": torch.empty(top_k, dtype=torch.float32, device=dev),
+               "topk_idx": torch.empty(top_k, dtype=torch.int64, device=dev)}
+        runs = {}
+        for name, spec, prec in (("plain_f32", spec32, "plain"), ("plain_f16", spec16, "plain"),
+                                 ("mixed_f16", spec16, "mixed")):
+            ms = _event_ms(lambda: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, precision=prec, out=out,
+                                                     workspace=ws), reps)
+            runs[name] = {"ms": ms, "evals_per_s": n * spec.n_seg / (ms * 1e-3)}
+            if name == "plain_f16":
+                plain_idx = torch.topk(out["stat"], 2000).indices.cpu().numpy()
+            if name == "mixed_f16":
+                mixed_stat = out["stat"].clone()
+                mixed_top = out["topk_idx"].cpu().numpy()
+        # statistic error of the mixed form against the oracle (same FP16 power)
+        rows = np.random.default_rng(20 + K).integers(0, n, 200_000)
+        C_rows = C_d[torch.from_numpy(rows).to(dev)].cpu().numpy()
+        o = oracle.score_tracks(P16, f0, U, C_rows, t_sft, 0)
+        rel = np.abs(mixed_stat[torch.from_numpy(rows).to(dev)].cpu().numpy() - o["stat"]) / np.abs(o["stat"])
+        # exact top-100 of the oracle over the candidate union
+        mixed_cand = torch.topk(mixed_stat, 2000).indices.cpu().numpy()
+        cand = np.unique(np.concatenate([plain_idx, mixed_cand]))
+        oc = oracle.score_tracks(P16, f0, U, C_d[torch.from_numpy(cand).to(dev)].cpu().numpy(), t_sft, top_k)
+        true_top = set(cand[oc["topk_idx"]].tolist())
+        progress(f"precision form K={K}: mixed {runs['mixed_f16']['ms']:.2f} ms, plain f32 {runs['plain_f32']['ms']:.2f} ms")
+        res[f"K{K}"] = {
+            **{k: v for k, v in runs.items()},
+            "speedup_mixed_vs_plain_f32": runs["plain_f32"]["ms"] / runs["mixed_f16"]["ms"],
+            "speedup_mixed_vs_plain_f16": runs["plain_f16"]["ms"] / runs["mixed_f16"]["ms"],
+            "stat_rel_err_vs_oracle": {"p50": float(np.quantile(rel, 0.5)), "p99": float(np.quantile(rel, 0.99)),
+                                       "max": float(rel.max()), "sample": int(rows.size)},
+            "top100_overlap": len(true_top & set(mixed_top.tolist())),
+        }
+        del C_d, out, mixed_stat
+        torch.cuda.empty_cache()
+    return res
+
+
+def batched_form(n_streams: int = 64, reps: int = 5) -> dict:
+    """Config 3: 64 uneven streams (3-12 months, 48-192 segments, 1e5-1e7
+    templates, top-256 each).  Stream by stream with score_tracks (plain FP32
+    and FP16) vs one batched launch (tile shape from the autotuner) replayed
+    from a captured HIP graph, plain and mixed, FP16 power."""
+    import torch
+    import paper_2510_20891_amd as emri
+    from paper_2510_20891_amd import autotune
+    dev = torch.device("cuda:0")
+    K, top_k = 8, 256
+    progress("batched form: generating streams")
+    streams = synth.batched_streams(n_streams, cfg=3)
+    progress("batched form: streams ready")
+    probs16, probs32, evals, total = [], [], 0, 0
+    for i, stv in enumerate(streams):
+        f0, U, sv, lo, hi = emri.build_basis(stv["tracks"], K)
+        x_d, psd_d = torch.from_numpy(stv["x"]).to(dev), torch.from_numpy(stv["psd"]).to(dev)
+        s16 = emri.build_sfts(x_d, stv["dt"], stv["n_sft"], psd_d, dtype="f16")
+        s32 = emri.build_sfts(x_d, stv["dt"], stv["n_sft"], psd_d, dtype="f32")
+        C = synth.device_coefficients(3, i, stv["n_tmpl"], lo, hi, dev)
+        f0_d, U_d = torch.from_numpy(f0).to(dev), torch.from_numpy(U).to(dev)
+        probs16.append(emri.Problem(s16, f0_d, U_d, C, top_k=top_k))
+        probs32.append(emri.Problem(s32, f0_d, U_d, C, top_k=top_k))
+        evals += stv["n_tmpl"] * s16.n_seg
+        total += stv["n_tmpl"]
+    ws = emri.Workspace()
+
+    def loop(probs, prec):
+        for pb in probs:
+            emri.score_tracks(pb.spec, pb.f0, pb.U, pb.coeffs, pb.top_k, precision=prec, workspace=ws)
+
+    out = {"workload": f"{n_streams} streams, {total} templates, {evals:.4g} template-segment evaluations",
+           "templates": total, "evals": evals}
+    for name, probs, prec in (("per_stream_plain_f32", probs32, "plain"), ("per_stream_plain_f16", probs16, "plain")):
+        ms = _event_ms(lambda: loop(probs, prec), reps)
+        out[name] = {"ms": ms, "evals_per_s": evals / (ms * 1e-3)}
+    progress(f"batched form: per-stream loops done")
+    for prec in ("plain", "mixed"):
+        plan, tune = autotune.tuned_plan(probs16, K, precision=prec, cache_path=None)
+        progress(f"batched form: tuned {prec}: {tune.table}")
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.run(side)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            plan.run()
+        ms = _event_ms(graph.replay, reps)
+        # every stream's top-k is the standalone call's
+        same = True
+        for pb in probs16[:8]:
+            ref = emri.score_tracks(pb.spec, pb.f0, pb.U, pb.coeffs, pb.top_k, precision=prec)
+            torch.cuda.synchronize()
+            same &= bool(torch.equal(ref["topk_idx"], pb.topk_idx) and torch.equal(ref["stat"], pb.stat))
+        out[f"batched_{prec}_f16_graph"] = {
+            "ms": ms, "evals_per_s": evals / (ms * 1e-3), "tile": {"rows_per_step": tune.rows_per_step,
+                                                                    "templates_per_lane": tune.templates_per_lane},
+            "autotune_table_ms": tune.table, "equals_standalone_first8": same}
+        del graph
+    base = out["per_stream_plain_f32"]["ms"]
+    out["speedup_batched_plain_vs_per_stream_f32"] = base / out["batched_plain_f16_graph"]["ms"]
+    out["speedup_batched_mixed_vs_per_stream_f32"] = base / out["batched_mixed_f16_graph"]["ms"]
+    del probs16, probs32
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_form(seconds: float = 32.0, warmup: float = 2.0, precision: str = "plain") -> dict:
+    """Config 4: 16 resident one-year FP16 spectrograms with a shared K = 8 basis;
+    Poisson arrivals at 2000 requests/s of floor(logU[256, 65536]) templates
+    against a uniform random stream, top-32 each; latency over the arrivals
+    after the first ``warmup`` seconds."""
+    import torch
+    import paper_2510_20891_amd as emri
+    from paper_2510_20891_amd.serving import GpuExecutor, Request, Server
+    dev = torch.device("cuda:0")
+    K, n_streams = 8, 16
+    specs, f0s, Us, segs = [], [], [], []
+    basis = None
+    for s in range(n_streams):
+        stv = synth.stream_config1(stream=s, cfg=4)
+        if basis is None:
+            basis = emri.build_basis(stv["tracks"], K)
+        x_d, psd_d = torch.from_numpy(stv["x"]).to(dev), torch.from_numpy(stv["psd"]).to(dev)
+        specs.append(emri.build_sfts(x_d, stv["dt"], stv["n_sft"], psd_d, dtype="f16"))
+        segs.append(specs[-1].n_seg)
+    f0, U, sv, lo, hi = basis
+    f0_d, U_d = torch.from_numpy(f0).to(dev), torch.from_numpy(U).to(dev)
+    pool = synth.coefficients(4, 0, 1 << 22, lo, hi)
+    reqs = [Request(r["rid"], r["stream"], pool[r["offset"]:r["offset"] + r["n"]], r["top_k"], r["t"])
+            for r in synth.serving_requests(n_streams, 2000.0, seconds, cfg=4, pool_size=pool.shape[0])]
+    slots, max_t, max_r = 3, 1 << 21, 512
+    ex = GpuExecutor(specs, [f0_d] * n_streams, [U_d] * n_streams, K, slots, max_t, max_r, 32, precision)
+    budget = 2 << 30
+    srv = Server(ex, K, hbm_budget=budget, max_batch_templates=max_t, max_requests=max_r, slots=slots,
+                 seg_counts=segs)
+    # warm the kernels and the plan path
+    warm = [Request(-1, 0, pool[:1024], 32, 0.0)]
+    Server(ex, K, budget, max_t, max_r, slots).run(warm)
+    progress(f"serving form: {len(reqs)} requests over {seconds:g} s")
+    srv.run(reqs)
+    st = srv.stats(reqs, warmup_s=warmup)
+    progress(f"serving form: p50 {st.latency_ms['p50']:.2f} ms, p99 {st.latency_ms['p99']:.2f} ms")
+    # a sample of results against standalone calls
+    g = np.random.default_rng(5)
+    same = True
+    for r in [reqs[i] for i in g.integers(0, len(reqs), 24)]:
+        ref = emri.score_tracks(specs[r.stream], f0_d, U_d, torch.from_numpy(r.coeffs).to(dev), 32, precision=precision)
+        torch.cuda.synchronize()
+        same &= bool(np.array_equal(ref["topk_idx"].cpu().numpy(), r.topk_idx)
+                     and np.array_equal(ref["topk_val"].cpu().numpy(), r.topk_val))
+    return {"workload": f"16 resident one-year FP16 spectrograms, Poisson 2000 req/s for {seconds:g} s "
+                        f"(first {warmup:g} s excluded), logU[256, 65536] templates, top-32, precision {precision}",
+            "requests": st.n_requests, "latency_ms": st.latency_ms,
+            "throughput_evals_per_s": st.evals / st.wall_s, "throughput_req_per_s": st.n_requests / st.wall_s,
+            "batches": st.batches, "mean_batch_requests": st.mean_batch_requests, "max_queue": st.max_queue,
+            "slots": slots, "hbm_budget_bytes": budget, "same_as_standalone_24_sampled": same}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +307,8 @@ def main() -> int:
     ap.add_argument("--templates", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1 << 21)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving forms")
+    ap.add_argument("--serve-seconds", type=float, default=32.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference for traffic counters)")
     args = ap.parse_args()
@@ -112,6 +321,7 @@ def main() -> int:
         return 2
 
     # ---- inputs (host), before any GPU initialisation -------------------------------
+    progress("generating the one-year stream")
     st = synth.stream_config1(stream=0)
     n = args.templates
     K, top_k = st["K"], st["top_k"]
@@ -127,7 +337,9 @@ def main() -> int:
     if not args.no_cpu:
         import oracle
         P_host = oracle.build_sfts(st["x"], st["dt"], st["n_sft"], st["psd"])
+        progress("timing the oracle on the host")
         cpu = cpu_baseline(P_host, f0, U, C, st["n_sft"] * st["dt"], min(args.cpu_sample, n))
+        progress(f"oracle: {cpu['value']:.3g} evals/s on {cpu['cores']} cores")
 
     # ---- GPU -------------------------------------------------------------------------
     import torch
@@ -220,6 +432,11 @@ def main() -> int:
         "end_to_end_with_h2d_evals_per_s": evals / (ms * 1e-3 + t_h2d),
         "topk_ms": ms - ms_kernel,
     }
+    if not args.no_forms:
+        del out, C_d
+        torch.cuda.empty_cache()
+        line["forms"] = {"precision": precision_form(st), "batched": batched_form(),
+                         "serving": serving_form(args.serve_seconds)}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -241,3 +241,40 @@ def batched_streams(n_streams: int = 64, cfg: int = 3) -> list[dict]:
         st["n_tmpl"] = n_tmpl
         out.append(st)
     return out
+
+
+def serving_requests(n_streams: int = 16, rate: float = 2000.0, seconds: float = 32.0, cfg: int = 4,
+                     pool_size: int = 1 << 22, top_k: int = 32) -> list[dict]:
+    """Poisson arrivals at ``rate`` per second for ``seconds``; each request draws a
+    template count floor(logU[256, 65536]), a stream uniform over ``n_streams``, and
+    an offset into a shared pool of ``pool_size`` coefficient vectors (the pool is
+    ``coefficients(cfg, 0, pool_size, ...)``; rows are reused across requests)."""
+    g = rng(cfg, 0, PURPOSE_REQUESTS)
+    out, t, rid = [], 0.0, 0
+    while True:
+        t += g.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        n = int(math.floor(math.exp(g.uniform(math.log(256.0), math.log(65536.0)))))
+        out.append(dict(rid=rid, t=t, stream=int(g.integers(0, n_streams)), n=n,
+                        offset=int(g.integers(0, pool_size - n + 1)), top_k=top_k))
+        rid += 1
+    return out
+
+
+def device_coefficients(cfg: int, stream: int, n: int, box_lo, box_hi, device="cuda"):
+    """``n`` coefficient vectors uniform in the box, drawn on the GPU (torch's
+    Philox generator seeded with (cfg, stream)); for benchmark batches too large
+    to draw on the host.  Same law as ``coefficients``, different stream of numbers."""
+    import torch
+    lo = torch.as_tensor(np.asarray(box_lo, dtype=np.float64), device=device)
+    hi = torch.as_tensor(np.asarray(box_hi, dtype=np.float64), device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(1_000_003 * int(cfg) + int(stream))
+    out = torch.empty((int(n), lo.numel()), dtype=torch.float32, device=device)
+    step = 1 << 22
+    for s in range(0, int(n), step):
+        m = min(step, int(n) - s)
+        u = torch.rand((m, lo.numel()), dtype=torch.float64, device=device, generator=gen)
+        out[s:s + m] = (lo + u * (hi - lo)).to(torch.float32)
+    return out
