@@ -85,6 +85,22 @@ def cpu_baseline(P, f0, U, C, t_sft, n_sample: int) -> dict:
                       f"{cores} worker processes, {wall:.2f} s wall"}
 
 
+def measured_traffic():
+    """HBM bytes per launch of the scoring kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or None if the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(PROFILE_TRAFFIC))
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+    except (OSError, ValueError, KeyError):
+        return None
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["kernel_sources_sha256"] else None
+
+
 def copy_calibration(nbytes: int) -> int:
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters scale the kernel's."""
     import torch
@@ -307,7 +323,8 @@ def main() -> int:
     ap.add_argument("--templates", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1 << 21)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-forms", action="store_true", help="skip the precision / batched / serving forms")
+    ap.add_argument("--forms", default="precision,batched,serving",
+                    help="comma-separated forms measured after the headline (precision, batched, serving, or none)")
     ap.add_argument("--serve-seconds", type=float, default=32.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference for traffic counters)")
@@ -398,12 +415,7 @@ def main() -> int:
     evals = n * n_seg
     b_eff = n * (4 * K + 4) + evals * 4 + n_seg * n_bins * 4
     achieved = b_eff / (ms_kernel * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(PROFILE_TRAFFIC):
-        try:
-            traffic = json.load(open(PROFILE_TRAFFIC)).get("hbm_bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    traffic = measured_traffic()
 
     line = {
         "metric": "template-segment evals/s (plain FP32 path, 1-year stream)",
@@ -432,11 +444,13 @@ def main() -> int:
         "end_to_end_with_h2d_evals_per_s": evals / (ms * 1e-3 + t_h2d),
         "topk_ms": ms - ms_kernel,
     }
-    if not args.no_forms:
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if forms:
         del out, C_d
         torch.cuda.empty_cache()
-        line["forms"] = {"precision": precision_form(st), "batched": batched_form(),
-                         "serving": serving_form(args.serve_seconds)}
+        runners = {"precision": lambda: precision_form(st), "batched": batched_form,
+                   "serving": lambda: serving_form(args.serve_seconds)}
+        line["forms"] = {f: runners[f]() for f in forms}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -327,7 +327,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_mixed_batched_kernel(cons
   }
 }
 
-constexpr int mixed_tpl(int K) { return K <= 4 ? 8 : (K <= 8 ? 6 : (K <= 12 ? 5 : 4)); }
+constexpr int mixed_tpl(int K) { return K <= 4 ? 8 : (K <= 8 ? 6 : 4); }
 
 template <typename Kern>
 hipError_t set_lds(Kern kern, size_t lds) {

@@ -335,8 +335,10 @@ __global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *
   prep_one(load_uniform(jobs + blockIdx.x));
 }
 
+// Templates per lane: as many FMA chains as the 256 VGPRs of two waves per SIMD
+// hold without spilling (a slot costs 2K + 5 registers).
 constexpr int tpl_for(int K) {
-  const int t = 180 / (2 * K + 3);
+  const int t = K <= 6 ? 190 / (2 * K + 5) : 180 / (2 * K + 3);
   return t > 16 ? 16 : (t < 1 ? 1 : t);
 }
 // a smaller tile for the autotuner: about two thirds of the default slots
