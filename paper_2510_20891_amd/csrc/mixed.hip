@@ -21,10 +21,14 @@
 // results, one per register: register r holds segment r of the step for every
 // lane, so the gathers of one register read one spectrogram row.
 //
-// Per (template, segment), with D the FP32 contraction plus phi:
-//     y = (double)D + (I + 1.5*2^52 + B/E)       (I = rint(f0 T), FP64, exact)
-//     bin address = med3(low word of y, range) * E
-// exactly as in the plain kernel, the FP64 rounding making rint(I + D).
+// Per (template, segment), with D the FP32 contraction plus phi, where
+// f0 T = I + phi exactly with I an even integer (FP64) and |phi| <= 1:
+//     bin = I + rint(D)
+// which equals the FP64 rounding rint(I + D) bit for bit (I + D is exact in
+// FP64, and an even I keeps half-to-even ties on the same side).  rint(D) is
+// one FP32 add: the bits of D + 1.5*2^23 are 0x4B400000 + rint(D) for
+// |D| < 2^22 (templates that could leave that range take an FP64 path), so
+//     address = E * (med3(bits, range - c) + c),  c = I + B/E - 0x4B400000.
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
 
@@ -91,7 +95,7 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
     double b = bnd[0];
 #pragma unroll
     for (int k = 0; k < K; ++k) b += __builtin_fabs((double)cf[k]) * bnd[1 + k];
-    wild |= !(b < 0.25 * kWildLimit);
+    wild |= !(b < 2097152.0);       // then |D| < 2^22 and FP32 rounding of D is exact
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
       unsigned short h[3][4];
@@ -151,6 +155,7 @@ __device__ __forceinline__ void step_operands(const unsigned char *tab, const Mi
     const MixedSeg m = load_uniform(ms + r0 + r);
     I[r] = m.I;
     phi[r] = m.phi;
+    asm volatile("" ::"s"(I[r]));   // keep the scalar loads here, ahead of the gathers' counted waits
   }
 }
 
@@ -177,6 +182,7 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
                                            double (&In)[4], float (&acc)[TPL], double (&sum)[TPL]) {
   constexpr int E = Elem<PT>::bytes;
   constexpr int NQ = kPairs * KG / 4 * TPL;       // products per quarter (lower bound)
+  static_assert(TPL < 16, "lgkmcnt holds at most 15 outstanding gathers");
   pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
   const bool more = r0 + 4 < p.n_seg;
   short4_t ua[3][KG];
@@ -184,45 +190,52 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
   step_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), more ? r0 + 4 : r0, ua, phi, In);
   __builtin_amdgcn_s_waitcnt(0xC07F);          // operands in registers before the interleaved region
   __builtin_amdgcn_sched_barrier(0);
-  typename Elem<PT>::raw_t v[TPL];
+  // gathers double-buffered: those of segment r are issued before waiting for
+  // those of segment r-1 (lgkmcnt(TPL): only LDS reads are outstanding here)
+  typename Elem<PT>::raw_t v[2][TPL];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const BufConst bc = buffer_consts<PT>(p, lds, half, r);
-    const double shift = Ic[r] + bc.magic;       // I + 1.5*2^52 + base: exact
+    // bits(D + 1.5*2^23) = 0x4B400000 + rint(D) for |D| < 2^22; the bin's LDS
+    // element is that plus cr = I + base - 0x4B400000, clamped in the shifted range
+    const int cr = (int)Ic[r] + bc.base - 0x4B400000;
+    const int lo = bc.lo - cr, hi = bc.hi - cr;
     int addr[TPL];
 #pragma unroll
     for (int s = 0; s < TPL; ++s) {
-      double y;
       if constexpr (WILD) {
         const double x = (double)dc[s][r] + Ic[r];
-        y = (__builtin_fabs(x) < kWildLimit) ? x + bc.magic : bc.magic - 2.0;
+        const double y = (__builtin_fabs(x) < kWildLimit) ? x + bc.magic : bc.magic - 2.0;
+        addr[s] = E * clamp_i32(low_word(y), bc.lo, bc.hi);
       } else {
-        y = (double)dc[s][r] + shift;
+        const int bits = __float_as_int(dc[s][r] + 12582912.0f);
+        addr[s] = E * (clamp_i32(bits, lo, hi) + cr);
       }
-      addr[s] = E * clamp_i32(low_word(y), bc.lo, bc.hi);
     }
     if (r == 0) products_part<KG, TPL, 0>(ua, phi, pc, dn);
     if (r == 1) products_part<KG, TPL, 1>(ua, phi, pc, dn);
     if (r == 2) products_part<KG, TPL, 2>(ua, phi, pc, dn);
     if (r == 3) products_part<KG, TPL, 3>(ua, phi, pc, dn);
     interleave_products<NQ>();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s = 0; s < TPL; ++s) v[r & 1][s] = Elem<PT>::raw(addr[s]);
+    __builtin_amdgcn_sched_barrier(0);
     if (r > 0) {
-      __builtin_amdgcn_s_waitcnt(0xC07F);        // lgkmcnt(0): gathers of segment r-1
+      __builtin_amdgcn_s_waitcnt(0xC07F | (TPL << 8));   // lgkmcnt(TPL): gathers of segment r-1
       __builtin_amdgcn_sched_barrier(0);
       if (r0 + r - 1 < p.n_seg) {
 #pragma unroll
-        for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+        for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[(r - 1) & 1][s], p.one);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) v[s] = Elem<PT>::raw(addr[s]);
-    __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_s_waitcnt(0xC07F);
   __builtin_amdgcn_sched_barrier(0);
   if (r0 + 3 < p.n_seg) {
 #pragma unroll
-    for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[s], p.one);
+    for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[1][s], p.one);
   }
   // FP32 runs of 8 segments (two steps), then FP64, as in the plain kernel
   if ((r0 & 4) != 0 || !more) {

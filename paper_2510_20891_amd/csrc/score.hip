@@ -297,7 +297,7 @@ __device__ __forceinline__ void prep_one(const PrepJob &job) {
   if (job.mtab) {
     // mixed-precision tables: U*T as three BF16 pieces (u0 + u1 + u2 carries
     // about 24 bits; each piece is the rounded FP64 remainder of the previous
-    // ones), and f0*T split into an integer and a fraction
+    // ones), and f0*T split into an even integer and a fraction
     const int KG = mixed_groups(K), n4 = (n_seg + 3) & ~3;
     unsigned short *tab = reinterpret_cast<unsigned short *>(job.mtab);
     for (int e = threadIdx.x; e < n4 * 4 * KG; e += blockDim.x) {
@@ -321,8 +321,8 @@ __device__ __forceinline__ void prep_one(const PrepJob &job) {
       m.pad = 0.0f;
       if (a < n_seg) {
         const double v = f0[a] * t_sft;
-        m.I = __builtin_rint(v);
-        m.phi = (float)(v - m.I);
+        m.I = 2.0 * __builtin_rint(0.5 * v);        // even integer nearest v (within 1)
+        m.phi = (float)(v - m.I);                   // exact difference, |phi| <= 1
       }
       ms[a] = m;
     }

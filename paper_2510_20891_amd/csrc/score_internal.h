@@ -38,8 +38,8 @@ struct ScoreParams {
   float one;                  // 1.0f: FP16 power is added as fma(P, one, acc), one instruction
 };
 
-// Mixed-precision form: per-segment offset f0*T = I + phi with I = rint(f0*T)
-// (FP64, an integer) and phi in [-1/2, 1/2] (FP32).
+// Mixed-precision form: per-segment offset f0*T = I + phi with I the even
+// integer nearest f0*T (FP64) and phi in [-1, 1] (FP32).
 struct MixedSeg {
   double I;
   float phi;
