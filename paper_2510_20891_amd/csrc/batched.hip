@@ -16,7 +16,7 @@ using namespace emri;
 
 namespace {
 
-constexpr size_t kLdsLimit = 163840;
+constexpr size_t kLdsLimit = 163840 - 256;   // LDS of a workgroup, less the static work-item slot
 constexpr uint32_t kPlanMagic = 0x454d5242u;   // "EMRB"
 
 // What score_batched_run needs, stored inside the caller's emri_batch_plan.
@@ -64,13 +64,13 @@ int check_problem(const emri_problem &pb, int i, int K, int dtype) {
 
 // Workspace layout of a batch.
 struct Layout {
-  size_t params, prep, topk_jobs, items, block_items, seg, bound, stat, topk, total;
+  size_t params, prep, topk_jobs, items, counter, seg, bound, stat, topk, total;
   std::vector<size_t> seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off;
 };
 
 int seg_stride_of(int K) { return (K + 2) & ~1; }
 
-Layout make_layout(const emri_problem *pbs, int n, int K, int max_items, int grid) {
+Layout make_layout(const emri_problem *pbs, int n, int K, int64_t max_items) {
   Layout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -81,8 +81,8 @@ Layout make_layout(const emri_problem *pbs, int n, int K, int max_items, int gri
   L.params = take(sizeof(ScoreParams) * n);
   L.prep = take(sizeof(PrepJob) * n);
   L.topk_jobs = take(sizeof(TopkJob) * n);
-  L.items = take(sizeof(BatchItem) * max_items);
-  L.block_items = take(sizeof(int) * (grid + 1));
+  L.items = take(sizeof(BatchItem) * (size_t)max_items);
+  L.counter = take(sizeof(int));
   L.seg = off;
   for (int i = 0; i < n; ++i) {
     const int ns = pbs[i].power.n_seg > 0 ? pbs[i].power.n_seg : 1;
@@ -113,7 +113,17 @@ int resolve_tpl(int K, int requested, int *tpl) {
   return fail(EMRI_EUNSUPPORTED, "templates_per_lane %d is not compiled for K = %d", requested, K);
 }
 
-int max_items_for(const emri_problem *pbs, int n, int grid) { return n + grid; }
+// Upper bound on the work items of a batch: one per tile of the smallest tile
+// any option of this K compiles.
+int64_t max_items_for(const emri_problem *pbs, int n, int K) {
+  int tpl = score_templates_per_lane(K, false);
+  if (K == 8 || K == 16) tpl = std::min(tpl, score_templates_per_lane(K, true));
+  if (K >= 1 && K <= MIXED_MAX_K) tpl = std::min(tpl, mixed_templates_per_lane(K));
+  const int64_t tile = (int64_t)tpl * SCORE_THREADS;
+  int64_t items = 0;
+  for (int i = 0; i < n; ++i) items += (pbs[i].n_tmpl + tile - 1) / tile;
+  return items > 0 ? items : 1;
+}
 
 }  // namespace
 
@@ -143,9 +153,7 @@ extern "C" int score_batched_workspace_size(const emri_problem *problems, int32_
     const int st = check_problem(problems[i], i, K, dtype);
     if (st) return st;
   }
-  // sized for the largest grid a gfx950 can have (256 compute units)
-  const int grid = 256;
-  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, grid), grid);
+  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, K));
   *bytes = L.total;
   return EMRI_OK;
 }
@@ -201,9 +209,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   }
   int cus = 0;
   if ((st = batch_grid(&cus)) != EMRI_OK) return st;
-  const int grid = std::min(cus, 256);
-
-  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, grid), grid);
+  const Layout L = make_layout(problems, n_problems, K, max_items_for(problems, n_problems, K));
   if (workspace_bytes < L.total)
     return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
   char *ws = reinterpret_cast<char *>(workspace);
@@ -258,49 +264,34 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     }
   }
 
-  // work split: tiles of templates, each weighted by its problem's segments
-  // (plus one for the tile's fixed cost), cut into `grid` contiguous shares
+  // work items: two tiles of one problem (a problem's odd last tile alone),
+  // in decreasing order of cost (tiles x (segments + 4)), so the launch ends
+  // on the cheapest items; workgroups claim them in this order
   const int64_t tile = tile_of(K, tpl);
-  std::vector<int64_t> tiles_of(n_problems);
-  double total = 0.0;
-  for (int i = 0; i < n_problems; ++i) {
-    tiles_of[i] = (problems[i].n_tmpl + tile - 1) / tile;
-    total += (double)tiles_of[i] * (problems[i].power.n_seg + 1);
-  }
   std::vector<BatchItem> items;
-  std::vector<int> block_items(grid + 1, 0);
-  {
-    int block = 0;
-    double acc = 0.0;
-    const double share = total / grid;
-    for (int i = 0; i < n_problems; ++i) {
-      const double w = (double)(problems[i].power.n_seg + 1);
-      int64_t t = 0;
-      while (t < tiles_of[i]) {
-        // tiles of problem i that still fit in this block's share
-        const double room = (block + 1) * share - acc;
-        int64_t take = (block == grid - 1) ? tiles_of[i] - t : (int64_t)std::floor(room / w + 0.5);
-        if (take <= 0) {
-          if (block < grid - 1) {
-            block_items[++block] = (int)items.size();
-            continue;
-          }
-          take = tiles_of[i] - t;
-        }
-        take = std::min(take, tiles_of[i] - t);
-        BatchItem it{};
-        it.stream = i;
-        it.begin = t * tile;
-        it.end = std::min(problems[i].n_tmpl, (t + take) * tile);
-        items.push_back(it);
-        acc += (double)take * w;
-        t += take;
-      }
+  std::vector<double> cost;
+  for (int i = 0; i < n_problems; ++i) {
+    const double w = (double)(((problems[i].power.n_seg + 3) & ~3) + 4);
+    for (int64_t t = 0; t * tile < problems[i].n_tmpl; t += 2) {
+      BatchItem it{};
+      it.stream = i;
+      it.begin = t * tile;
+      it.end = std::min(problems[i].n_tmpl, (t + 2) * tile);
+      items.push_back(it);
+      cost.push_back(w * (double)((it.end - it.begin + tile - 1) / tile));
     }
-    for (int b = block + 1; b <= grid; ++b) block_items[b] = (int)items.size();
   }
-  if ((int)items.size() > max_items_for(problems, n_problems, grid))
+  std::vector<int> order(items.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  {
+    std::vector<BatchItem> sorted(items.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = items[order[k]];
+    items.swap(sorted);
+  }
+  if ((int64_t)items.size() > max_items_for(problems, n_problems, K) || items.size() > (size_t)INT32_MAX)
     return fail(EMRI_ERANGE, "work list longer than planned");
+  const int grid = (int)std::min<size_t>((size_t)std::min(cus, 1024), std::max<size_t>(items.size(), 1));
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t err = hipSuccess;
@@ -311,7 +302,6 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   copy(L.prep, preps.data(), sizeof(PrepJob) * preps.size());
   copy(L.topk_jobs, topks.data(), sizeof(TopkJob) * topks.size());
   copy(L.items, items.data(), sizeof(BatchItem) * items.size());
-  copy(L.block_items, block_items.data(), sizeof(int) * block_items.size());
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched plan copies: %s", hipGetErrorString(err));
 
   PlanData pd{};
@@ -322,7 +312,8 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.max_topk_n = max_topk_n;
   pd.launch.params = reinterpret_cast<const ScoreParams *>(ws + L.params);
   pd.launch.items = reinterpret_cast<const BatchItem *>(ws + L.items);
-  pd.launch.block_items = reinterpret_cast<const int *>(ws + L.block_items);
+  pd.launch.counter = reinterpret_cast<int *>(ws + L.counter);
+  pd.launch.n_items = (int)items.size();
   pd.launch.grid = grid;
   pd.launch.K = K;
   pd.launch.dtype = dtype;
@@ -345,7 +336,7 @@ extern "C" int score_batched_run(const emri_batch_plan *plan, void *hip_stream) 
   std::memcpy(&pd, plan, sizeof pd);
   if (pd.magic != kPlanMagic) return fail(EMRI_EINVAL, "plan was not made by score_batched_plan");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-  hipError_t err = launch_score_prep_batched(pd.prep_jobs, pd.n_problems, stream);
+  hipError_t err = launch_score_prep_batched(pd.prep_jobs, pd.n_problems, pd.launch.counter, stream);
   if (err == hipSuccess && pd.has_work)
     err = pd.launch.mixed ? launch_score_mixed_batched(pd.launch, stream) : launch_score_batched(pd.launch, stream);
   if (err == hipSuccess && pd.n_topk > 0) {

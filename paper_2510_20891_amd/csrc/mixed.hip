@@ -321,20 +321,24 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_mixed_kernel(ScoreParams 
   score_range_mixed<K, TPL, PT>(p, lds, j_begin, j_end);
 }
 
-// Batched form of the mixed kernel (same work items as the plain batched kernel).
+// Batched form of the mixed kernel (work items claimed as in the plain
+// batched kernel; the piece table is reloaded when the stream changes).
 template <int K, int TPL, typename PT>
 __global__ __launch_bounds__(SCORE_THREADS) void score_mixed_batched_kernel(const ScoreParams *__restrict__ params,
                                                                             const BatchItem *__restrict__ items,
-                                                                            const int *__restrict__ block_items) {
+                                                                            int n_items, int *counter) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  typedef const __attribute__((address_space(4))) int *const_ints;
-  const int first = ((const_ints)block_items)[blockIdx.x];
-  const int last = ((const_ints)block_items)[blockIdx.x + 1];
-  for (int it = first; it < last; ++it) {
+  __shared__ int slot;
+  int table_of = -1;
+  for (;;) {
+    const int it = claim_item(counter, &slot);
+    if (it >= n_items) break;
     const BatchItem item = load_uniform(items + it);
     const ScoreParams p = load_uniform(params + item.stream);
-    __syncthreads();              // the previous item's last reads of the table are done
-    load_table(p, lds);
+    if (item.stream != table_of) {     // claim_item's barriers order this after the last reads
+      load_table(p, lds);
+      table_of = item.stream;
+    }
     init_lds(p, staging_base(p, lds));
     score_range_mixed<K, TPL, PT>(p, lds, item.begin, item.end);
   }
@@ -362,7 +366,7 @@ hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
   auto kern = score_mixed_batched_kernel<K, mixed_tpl(K), PT>;
   hipError_t err = set_lds(kern, b.lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.n_items, b.counter);
   return hipGetLastError();
 }
 

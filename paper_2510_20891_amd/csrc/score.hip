@@ -189,19 +189,19 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p
   score_range<K, TPL, PT>(p, lds, j_begin, j_end);
 }
 
-// Batched form: one persistent launch over many streams.  Workgroup g walks
-// the work items [block_items[g], block_items[g+1]); an item is a range of
-// one stream's templates, and every stream carries its own spectrogram,
-// constants, bin range and staging geometry.
+// Batched form: one persistent launch over many streams.  Workgroups claim
+// work items (a range of one stream's templates) until the table is
+// exhausted; every stream carries its own spectrogram, constants, bin range
+// and staging geometry.
 template <int K, int TPL, typename PT>
 __global__ __launch_bounds__(SCORE_THREADS) void score_batched_kernel(const ScoreParams *__restrict__ params,
                                                                       const BatchItem *__restrict__ items,
-                                                                      const int *__restrict__ block_items) {
+                                                                      int n_items, int *counter) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  typedef const __attribute__((address_space(4))) int *const_ints;
-  const int first = ((const_ints)block_items)[blockIdx.x];
-  const int last = ((const_ints)block_items)[blockIdx.x + 1];
-  for (int it = first; it < last; ++it) {
+  __shared__ int slot;
+  for (;;) {
+    const int it = claim_item(counter, &slot);
+    if (it >= n_items) break;
     const BatchItem item = load_uniform(items + it);
     const ScoreParams p = load_uniform(params + item.stream);
     init_lds(p, lds);
@@ -331,7 +331,8 @@ __device__ __forceinline__ void prep_one(const PrepJob &job) {
 
 __global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) { prep_one(job); }
 
-__global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs) {
+__global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs, int *counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;     // work-item counter of the scoring launch
   prep_one(load_uniform(jobs + blockIdx.x));
 }
 
@@ -371,13 +372,13 @@ hipError_t launch_batched_k(const BatchLaunch &b, hipStream_t stream) {
     if (b.tpl == tpl_alt(K)) {
       auto kern = score_batched_kernel<K, tpl_alt(K), PT>;
       if ((err = set_lds(kern, b.lds)) != hipSuccess) return err;
-      hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
+      hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.n_items, b.counter);
       return hipGetLastError();
     }
   }
   auto kern = score_batched_kernel<K, tpl_for(K), PT>;
   if ((err = set_lds(kern, b.lds)) != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.block_items);
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(SCORE_THREADS), b.lds, stream, b.params, b.items, b.n_items, b.counter);
   return hipGetLastError();
 }
 
@@ -420,9 +421,9 @@ hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream) {
   return hipGetLastError();
 }
 
-hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, hipStream_t stream) {
+hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, int *counter, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(score_prep_batched_kernel, dim3(n_jobs), dim3(256), 0, stream, jobs);
+  hipLaunchKernelGGL(score_prep_batched_kernel, dim3(n_jobs), dim3(256), 0, stream, jobs, counter);
   return hipGetLastError();
 }
 

@@ -67,7 +67,8 @@ struct Staging {
 bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_max, int rows_per_step,
                   size_t lds_limit, Staging *out);
 
-// A range of one stream's templates, scored by one workgroup of the batched launch.
+// A range of one stream's templates, scored by one workgroup of the batched
+// launch.  Workgroups claim items in table order through an atomic counter.
 struct BatchItem {
   int32_t stream;
   int32_t pad;
@@ -89,10 +90,10 @@ struct PrepJob {
 struct BatchLaunch {
   const ScoreParams *params;
   const BatchItem *items;
-  const int *block_items;
-  int grid, K, dtype, tpl;
+  int *counter;               // next item to claim (reset to 0 by the prep kernel of each run)
+  int n_items, grid, K, dtype, tpl;
+  int mixed;
   size_t lds;
-  int mixed, pad;
 };
 
 // Read a small trivially copyable struct from read-only device memory with
@@ -111,7 +112,7 @@ __device__ __forceinline__ T load_uniform(const T *src) {
 
 int score_templates_per_lane(int K, bool alt);
 hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream);
-hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, hipStream_t stream);
+hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, int *counter, hipStream_t stream);
 hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, int grid, size_t lds,
                         hipStream_t stream);
 hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream);

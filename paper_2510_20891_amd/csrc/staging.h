@@ -149,6 +149,16 @@ __device__ __forceinline__ void init_lds(const ScoreParams &p, unsigned char *ld
   if (threadIdx.x < 3 * kLeadIn) lds[(threadIdx.x / kLeadIn) * p.half_bytes + threadIdx.x % kLeadIn] = 0;
 }
 
+// Next work item of a dynamically scheduled launch: one atomic per workgroup,
+// broadcast through `slot` (LDS); wave-uniform result.
+__device__ __forceinline__ int claim_item(int *counter, int *slot) {
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = __builtin_amdgcn_readfirstlane(*slot);
+  __syncthreads();             // every wave has read the slot before it is reused
+  return it;
+}
+
 // BF16 with round-to-nearest-even from FP32 (NaN stays NaN), and back.
 __device__ __forceinline__ unsigned short bf16_rne(float f) {
   unsigned u = __float_as_uint(f);
