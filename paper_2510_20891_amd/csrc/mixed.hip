@@ -288,26 +288,38 @@ __device__ __forceinline__ unsigned char *staging_base(const ScoreParams &p, uns
   return lds + ((p.mtab_bytes + 1023) & ~1023);
 }
 
+template <int K, int T, typename PT>
+__device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned char *lds, unsigned char *stage,
+                                                 int64_t t0, int64_t j_end) {
+  constexpr int KG = (K + 3) / 4;
+  Pieces<KG, T> pc;
+  const bool wild = load_pieces<K, KG, T>(p, t0, j_end, pc);
+  double sum[T];
+#pragma unroll
+  for (int s = 0; s < T; ++s) sum[s] = 0.0;
+  if (__any(wild))
+    run_tile_mixed<KG, T, PT, true>(p, lds, stage, pc, sum);
+  else
+    run_tile_mixed<KG, T, PT, false>(p, lds, stage, pc, sum);
+#pragma unroll
+  for (int s = 0; s < T; ++s) {
+    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + threadIdx.x;
+    if (j < j_end) p.stat[j] = (float)sum[s];
+  }
+}
+
+// Tiles of TPL slots; a last tile that fits in half as many slots runs with half.
 template <int K, int TPL, typename PT>
 __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
                                                   int64_t j_end) {
-  constexpr int KG = (K + 3) / 4;
+  constexpr int TAIL = (TPL + 1) / 2;
   unsigned char *stage = staging_base(p, lds);
   for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * SCORE_THREADS) {
-    Pieces<KG, TPL> pc;
-    const bool wild = load_pieces<K, KG, TPL>(p, t0, j_end, pc);
-    double sum[TPL];
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) sum[s] = 0.0;
-    if (__any(wild))
-      run_tile_mixed<KG, TPL, PT, true>(p, lds, stage, pc, sum);
-    else
-      run_tile_mixed<KG, TPL, PT, false>(p, lds, stage, pc, sum);
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) {
-      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + threadIdx.x;
-      if (j < j_end) p.stat[j] = (float)sum[s];
+    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * SCORE_THREADS) {
+      score_tile_mixed<K, TAIL, PT>(p, lds, stage, t0, j_end);
+      break;
     }
+    score_tile_mixed<K, TPL, PT>(p, lds, stage, t0, j_end);
   }
 }
 

@@ -128,55 +128,69 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   }
 }
 
-// Score templates [j_begin, j_end) of one stream (the workgroup's share).
+// One tile of T slots (T x 512 templates starting at t0, clipped to j_end).
+template <int K, int T, typename PT>
+__device__ __forceinline__ void score_tile(const ScoreParams &p, unsigned char *lds, int64_t t0, int64_t j_end,
+                                           const double (&bound_u)[K > 0 ? K : 1], double bound_f0) {
+  const int tid = threadIdx.x;
+  double c[T][K > 0 ? K : 1];
+  bool wild = false;
+#pragma unroll
+  for (int s = 0; s < T; ++s) {
+    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+    const bool live = j < j_end;
+    float cf[K > 0 ? K : 1];
+    if constexpr (K % 4 == 0) {
+#pragma unroll
+      for (int k = 0; k < K; k += 4) {
+        const float4 v = live ? reinterpret_cast<const float4 *>(p.coeffs + (size_t)j * K)[k / 4]
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        cf[k] = v.x; cf[k + 1] = v.y; cf[k + 2] = v.z; cf[k + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
+    }
+    double bnd = bound_f0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      c[s][k] = (double)cf[k];
+      bnd += __builtin_fabs(c[s][k]) * bound_u[k];
+    }
+    wild |= !(bnd < 0.5 * kWildLimit);
+  }
+  double sum[T];
+#pragma unroll
+  for (int s = 0; s < T; ++s) sum[s] = 0.0;
+  if (__any(wild))
+    run_tile<K, T, PT, true>(p, lds, c, sum);
+  else
+    run_tile<K, T, PT, false>(p, lds, c, sum);
+#pragma unroll
+  for (int s = 0; s < T; ++s) {
+    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+    if (j < j_end) p.stat[j] = (float)sum[s];
+  }
+}
+
+// Score templates [j_begin, j_end) of one stream (the workgroup's share) in
+// tiles of TPL slots; a last tile that fits in half as many slots runs with
+// half (the per-template arithmetic and order do not depend on the tile).
 template <int K, int TPL, typename PT>
 __device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
                                             int64_t j_end) {
-  const int tid = threadIdx.x;
+  constexpr int TAIL = (TPL + 1) / 2;
   const_dptr bnd_src = (const_dptr)p.bound;
   double bound_u[K > 0 ? K : 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) bound_u[k] = bnd_src[1 + k];
   const double bound_f0 = bnd_src[0];
   for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * SCORE_THREADS) {
-    double c[TPL][K > 0 ? K : 1];
-    bool wild = false;
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) {
-      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
-      const bool live = j < j_end;
-      float cf[K > 0 ? K : 1];
-      if constexpr (K % 4 == 0) {
-#pragma unroll
-        for (int k = 0; k < K; k += 4) {
-          const float4 v = live ? reinterpret_cast<const float4 *>(p.coeffs + (size_t)j * K)[k / 4]
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-          cf[k] = v.x; cf[k + 1] = v.y; cf[k + 2] = v.z; cf[k + 3] = v.w;
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
-      }
-      double bnd = bound_f0;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        c[s][k] = (double)cf[k];
-        bnd += __builtin_fabs(c[s][k]) * bound_u[k];
-      }
-      wild |= !(bnd < 0.5 * kWildLimit);
+    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * SCORE_THREADS) {
+      score_tile<K, TAIL, PT>(p, lds, t0, j_end, bound_u, bound_f0);
+      break;
     }
-    double sum[TPL];
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) sum[s] = 0.0;
-    if (__any(wild))
-      run_tile<K, TPL, PT, true>(p, lds, c, sum);
-    else
-      run_tile<K, TPL, PT, false>(p, lds, c, sum);
-#pragma unroll
-    for (int s = 0; s < TPL; ++s) {
-      const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
-      if (j < j_end) p.stat[j] = (float)sum[s];
-    }
+    score_tile<K, TPL, PT>(p, lds, t0, j_end, bound_u, bound_f0);
   }
 }
 
