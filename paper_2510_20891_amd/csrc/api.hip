@@ -141,7 +141,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   const bool validate = bins != nullptr || n_near_tie != nullptr;
 
   hipError_t err = hipSuccess;
-  if (power->n_seg > 0 || validate) {
+  if (power->n_seg > 0 || validate || top_k > 0) {
     PrepJob job{};
     job.f0 = f0;
     job.U = U;
@@ -156,6 +156,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
       job.mtab = ws + L.mtab_off;
       job.mseg = ws + L.mseg_off;
     }
+    if (top_k > 0) job.topk = reinterpret_cast<TopkState *>(ws + L.topk_off);
     err = launch_score_prep(job, stream);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score prep launch: %s", hipGetErrorString(err));
   }

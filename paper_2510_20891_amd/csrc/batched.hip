@@ -259,6 +259,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
       pj.mseg = ws + L.mseg_off[i];
     }
     if (pb.top_k > 0) {
+      pj.topk = reinterpret_cast<TopkState *>(ws + L.topk_off[i]);
       topks.push_back(make_topk_job(p.stat, pb.n_tmpl, pb.top_k, pb.topk_val, pb.topk_idx, ws + L.topk_off[i]));
       max_topk_n = std::max(max_topk_n, pb.n_tmpl);
     }

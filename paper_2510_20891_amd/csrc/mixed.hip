@@ -63,8 +63,8 @@ struct Pieces {
 };
 
 // Load and split the coefficients of this lane's TPL templates of tile t0.
-// Returns true if any of them could place a track outside |x| < 2^25 bins
-// (huge or non-finite values), from the per-segment bound of prep.
+// Returns true if any of them could place a track at |x| >= 2^21 bins (huge
+// or non-finite values), from the per-segment bounds of prep.
 template <int K, int KG, int TPL>
 __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, int64_t j_end, Pieces<KG, TPL> &pc) {
   const int tid = threadIdx.x;

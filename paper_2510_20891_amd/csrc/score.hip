@@ -281,13 +281,21 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
 
 // Per-segment constants f0*T, U*T (FP64) and the bounds of the wild-template
 // test: bound[0] = max |f0 T|, bound[1+k] = max_alpha |U[alpha,k] T| (+inf if
-// an entry is not finite).  Also clears the near-tie counter.  One workgroup.
+// an entry is not finite).  Also clears the near-tie counter and resets the
+// top-k state of the call.  One workgroup of 256 threads.
+__device__ __forceinline__ double abs_bound(double v) {
+  const double av = __builtin_fabs(v);
+  return av <= 1.7976931348623157e308 ? av : __builtin_inf();     // NaN and inf: +inf
+}
+
 __device__ __forceinline__ void prep_one(const PrepJob &job) {
-  __shared__ double red[256];
+  __shared__ double red[4][EMRI_MAX_K + 1];
   const double *f0 = job.f0, *U = job.U;
   const int K = job.K, n_seg = job.n_seg, stride = job.seg_stride;
   const double t_sft = job.t_sft;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0 && job.near_tie) *job.near_tie = 0ull;
+  if (job.topk) topk_state_reset(job.topk);
   for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
     job.seg[(size_t)a * stride] = f0[a] * t_sft;
     for (int k = 0; k < K; ++k) job.seg[(size_t)a * stride + 1 + k] = U[(size_t)a * K + k] * t_sft;
@@ -295,18 +303,20 @@ __device__ __forceinline__ void prep_one(const PrepJob &job) {
   for (int col = 0; col <= K; ++col) {
     double m = 0.0;
     for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
-      const double v = col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft;
-      const double av = __builtin_fabs(v);
-      m = (av <= 1.7976931348623157e308) ? (av > m ? av : m) : __builtin_inf();
+      const double b = abs_bound(col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft);
+      m = b > m ? b : m;
     }
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + w] ? red[threadIdx.x] : red[threadIdx.x + w];
-      __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(m, off, 64);
+      m = o > m ? o : m;
     }
-    if (threadIdx.x == 0) job.bound[col] = red[0];
-    __syncthreads();
+    if (lane == 0) red[wave][col] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x <= K) {
+    double m = red[0][threadIdx.x];
+    for (int w = 1; w < 4; ++w) m = red[w][threadIdx.x] > m ? red[w][threadIdx.x] : m;
+    job.bound[threadIdx.x] = m;
   }
   if (job.mtab) {
     // mixed-precision tables: U*T as three BF16 pieces (u0 + u1 + u2 carries

@@ -10,7 +10,7 @@ namespace emri {
 constexpr int SCORE_THREADS = 512;   // one persistent workgroup of 8 waves per CU
 constexpr int EMRI_MAX_K = 32;
 constexpr int EMRI_MAX_TOPK = 4096;
-constexpr int TOPK_HIST = 2048;
+constexpr int TOPK_HIST = 4096;        // bins of one radix pass (digits of at most 12 bits)
 constexpr int SCORE_LDS_LEAD = 16;   // bytes ahead of each LDS half's first row
 constexpr int SCORE_WAVES = SCORE_THREADS / 64;
 
@@ -76,6 +76,8 @@ struct BatchItem {
 };
 
 // Everything the per-segment constants kernel needs for one stream.
+struct TopkState;
+
 struct PrepJob {
   const double *f0, *U;
   double *seg, *bound;
@@ -84,6 +86,7 @@ struct PrepJob {
   int K, n_seg, seg_stride, pad;
   void *mtab;                  // mixed-precision tables, or null
   void *mseg;
+  TopkState *topk;             // top-k state to reset, or null
 };
 
 // Launch shape of a batched scoring launch (device tables live in the workspace).
@@ -121,6 +124,13 @@ int mixed_templates_per_lane(int K);
 hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream);
 hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream);
 
+// Top-k state of one job.  Only hist, arrive and done (all zero) must hold
+// before the first pass: topk_state_reset, run by the prep kernels ahead of the
+// scores, sets them, and every pass leaves them so again; the other fields are
+// written by the passes before they are read.
+constexpr int TOPK_ARRIVE_GROUPS = 32;   // arrival counters per pass (one per 32nd of the workgroups)
+constexpr int TOPK_ARRIVE_STRIDE = 32;   // words between counters: one 128-byte line each
+
 struct TopkState {
   uint32_t key_prefix;        // bits of the k-th largest key found so far
   uint32_t need;              // elements still to take among keys matching the prefix
@@ -129,9 +139,18 @@ struct TopkState {
   uint32_t tie_mode;          // 1: keys equal to the threshold are cut by index
   uint32_t count;             // compaction cursor
   uint32_t eq_count;          // number of keys equal to the threshold
-  uint32_t pad;
+  uint32_t done;              // groups of workgroups of the current pass that have finished
+  uint32_t pad[24];
+  uint32_t arrive[TOPK_ARRIVE_GROUPS * TOPK_ARRIVE_STRIDE];   // finished workgroups per group
   uint32_t hist[TOPK_HIST];
 };
+
+// Called by every thread of one workgroup.
+__device__ __forceinline__ void topk_state_reset(TopkState *st) {
+  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) st->hist[b] = 0u;
+  for (int g = threadIdx.x; g < TOPK_ARRIVE_GROUPS; g += blockDim.x) st->arrive[g * TOPK_ARRIVE_STRIDE] = 0u;
+  if (threadIdx.x == 0) st->done = 0u;
+}
 
 // One top-k problem: the statistic, its length, and where state and results live.
 struct TopkJob {

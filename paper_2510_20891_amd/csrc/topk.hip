@@ -5,11 +5,15 @@
 // Radix select on an order-preserving 32-bit key of S: three histogram passes
 // (11, 11 and 10 bits) find the key T of the k-th element and how many of the
 // elements equal to T belong to the top-k.  If T is shared by more elements
-// than are needed, three more passes select the needed count of smallest
-// template indices among them.  One compaction pass then gathers exactly k
-// (key, index) pairs, and one workgroup sorts them with a bitonic network in
-// LDS.  All passes stream the statistic with 16-byte loads; histograms are
-// built in LDS and merged with one atomic per non-empty bin per workgroup.
+// than are needed, index passes (digits of at most 12 bits over the bits an
+// index of this length has) select the needed count of smallest template
+// indices among them; otherwise they return at once.  One compaction pass then
+// gathers exactly k (key, index) pairs and sorts them with a bitonic network in
+// LDS.  Every pass streams the statistic with 16-byte loads and builds its
+// histogram in LDS, merged with one atomic per non-empty bin per workgroup.
+// The last workgroup of a pass to finish (an arrival counter in the state; no
+// workgroup ever waits for another) picks the digit for the next pass, or, in
+// the compaction pass, sorts the candidates, so a top-k is 4 to 7 launches.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -19,6 +23,18 @@ namespace emri {
 namespace {
 
 constexpr int HIST_THREADS = 256;
+
+// Device-memory views: loads and stores through them are global (not flat)
+// instructions, so the compiler need not order them against LDS accesses.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ gmem<T> *global(T *p) {
+  return (gmem<T> *)p;
+}
+constexpr int INDEX_DIGIT = 12;               // widest index digit (TOPK_HIST bins)
+constexpr int RANK_SORT_MAX = 1024;           // up to this many winners are ordered by rank counting
 
 __device__ __forceinline__ uint32_t order_key(float v) {
   uint32_t u = __float_as_uint(v);
@@ -31,35 +47,179 @@ __device__ __forceinline__ float key_value(uint32_t k) {
   return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-// Digit layout: keys use (shift, width) = (21,11), (10,11), (0,10);
-// indices (31-bit) use (20,11), (10,10), (0,10).
-__device__ __forceinline__ void key_digit(int pass, int *shift, int *width) {
-  *shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-  *width = pass == 2 ? 10 : 11;
-}
-__device__ __forceinline__ void idx_digit(int pass, int *shift, int *width) {
-  *shift = pass == 0 ? 20 : (pass == 1 ? 10 : 0);
-  *width = pass == 0 ? 11 : 10;
-}
+// Calls f(i, stat[i]) for this workgroup's share of the statistic.  Each
+// thread keeps STREAM 16-byte loads in flight (a pass is one short stream over
+// the vector, so latency, not bandwidth, sets its time otherwise).
+constexpr int STREAM = 4;
 
 template <typename F>
 __device__ __forceinline__ void for_each_stat(const float *__restrict__ stat, int64_t n, F &&f) {
   const int64_t n4 = n >> 2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += stride) {
-    const float4 v = reinterpret_cast<const float4 *>(stat)[q];
-    f(4 * q + 0, v.x);
-    f(4 * q + 1, v.y);
-    f(4 * q + 2, v.z);
-    f(4 * q + 3, v.w);
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const gmem<const f4> *s4 = global(reinterpret_cast<const f4 *>(stat));
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < n4; q0 += STREAM * stride) {
+    f4 v[STREAM];
+#pragma unroll
+    for (int u = 0; u < STREAM; ++u) {
+      const int64_t q = q0 + u * stride;
+      v[u] = q < n4 ? s4[q] : f4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < STREAM; ++u) {
+      const int64_t q = q0 + u * stride;
+      if (q < n4) {
+        f(4 * q + 0, v[u].x);
+        f(4 * q + 1, v[u].y);
+        f(4 * q + 2, v[u].z);
+        f(4 * q + 3, v[u].w);
+      }
+    }
   }
   for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) f(i, stat[i]);
 }
 
-__device__ __forceinline__ void flush_hist(uint32_t *lh, uint32_t *gh) {
+// Count `bin` in the LDS histogram if `in`.  Statistics crowd into a few bins
+// of the leading digit (and tied keys into runs of neighbouring indices), so
+// with AGGREGATE the lanes of a wave that share the bin of the first lane still
+// counting add their count with one atomic; after three such rounds the rest
+// add one each.  Later key digits spread over their bins and count directly.
+template <bool AGGREGATE>
+__device__ __forceinline__ void hist_add(uint32_t *lh, uint32_t bin, bool in) {
+  if (!in) return;
+  for (int round = 0; round < (AGGREGATE ? 3 : 0); ++round) {
+    const uint32_t lb = __builtin_amdgcn_readfirstlane(bin);     // first lane still counting
+    const unsigned long long group = __ballot(bin == lb);
+    if (bin == lb) {
+      if (__lane_id() == __ffsll(group) - 1) atomicAdd(&lh[lb], (uint32_t)__popcll(group));
+      return;
+    }
+  }
+  atomicAdd(&lh[bin], 1u);
+}
+
+// Histogram of the first key digit (sign, exponent and two mantissa bits).
+// Across a statistic vector it takes a few neighbouring values, so an LDS
+// atomic per element would serialise on them.  Each thread counts the 8 bins
+// of its wave's window (starting 3 below the bin of the wave's first element)
+// in 8-bit fields of one 64-bit register, over the 4 * STREAM elements of one
+// group of loads; then the wave adds the fields up (16 bits each: at most 64 x
+// 16 per bin) and one lane adds the 8 sums to the LDS histogram.  Elements
+// outside the window are counted one by one.  Every lane of a wave runs the
+// same number of groups (those the wave's first lane runs), so the wave-wide
+// sums see all 64 lanes.
+__device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, uint32_t *lh, int shift, uint32_t mask) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  const gmem<const f4> *s4 = global(reinterpret_cast<const f4 *>(stat));
+  const int64_t n4 = n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int lane = (int)__lane_id();
+  uint32_t base = 0u;
+  bool have_base = false;
+  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 - lane < n4; q0 += STREAM * stride) {
+    f4 v[STREAM];
+#pragma unroll
+    for (int u = 0; u < STREAM; ++u) {
+      const int64_t q = q0 + u * stride;
+      v[u] = q < n4 ? s4[q] : f4{0.f, 0.f, 0.f, 0.f};
+    }
+    if (!have_base) {                // the wave's first lane has an element here
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane((order_key(v[0].x) >> shift) & mask);
+      base = b0 >= 3u ? b0 - 3u : 0u;
+      have_base = true;
+    }
+    uint64_t packed = 0ull;
+#pragma unroll
+    for (int u = 0; u < STREAM; ++u) {
+      if (q0 + u * stride < n4) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const uint32_t bin = (order_key(v[u][c]) >> shift) & mask;
+          const uint32_t d = bin - base;
+          if (d < 8u) packed += 1ull << (8u * d);
+          else atomicAdd(&lh[bin], 1u);
+        }
+      }
+    }
+    unsigned long long even = packed & 0x00ff00ff00ff00ffull;          // bins base+0, +2, +4, +6
+    unsigned long long odd = (packed >> 8) & 0x00ff00ff00ff00ffull;    // bins base+1, +3, +5, +7
+    for (int off = 32; off > 0; off >>= 1) {
+      even += __shfl_xor(even, off, 64);
+      odd += __shfl_xor(odd, off, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const uint32_t ce = (uint32_t)(even >> (16 * f)) & 0xffffu, co = (uint32_t)(odd >> (16 * f)) & 0xffffu;
+        if (ce) atomicAdd(&lh[base + 2 * f], ce);
+        if (co) atomicAdd(&lh[base + 2 * f + 1], co);
+      }
+    }
+  }
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    atomicAdd(&lh[(order_key(stat[i]) >> shift) & mask], 1u);
+}
+
+__device__ __forceinline__ void clear_hist(uint32_t *lh, int nb) {
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) lh[b] = 0u;
   __syncthreads();
-  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x)
+}
+
+__device__ __forceinline__ void flush_hist(const uint32_t *lh, uint32_t *gh, int nb) {
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
     if (lh[b]) atomicAdd(&gh[b], lh[b]);
+}
+
+// Everything one workgroup leaves for the last one of its pass goes through
+// agent-scope atomics, which are coherent across the chip's L2 caches without
+// cache maintenance: histogram bins and counters by read-modify-write; the
+// merged bins and the candidates by atomic loads and stores.  A workgroup
+// waits until its own atomics have completed (vmcnt), then counts itself on
+// its group's arrival counter (workgroup b is in group b mod 32); the last of
+// a group counts the group on `done`, and the workgroup that completes `done`
+// reads after that, so it sees every other workgroup's completed atomics.
+// The two levels keep any one counter to 32 arrivals: atomics on one address
+// are serialised, and all workgroups of a pass finish at about the same time.
+// No workgroup waits for another, and no pass writes back or invalidates an L2
+// cache (an agent-scope fence would, once per workgroup).
+__device__ __forceinline__ bool last_to_finish(TopkState *st) {
+  __shared__ uint32_t last;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t G = TOPK_ARRIVE_GROUPS, g = blockIdx.x % G;
+    const uint32_t members = (gridDim.x - g + G - 1) / G;      // workgroups b < gridDim.x with b mod G == g
+    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
+    uint32_t l = 0u;
+    if (atomicAdd(&st->arrive[g * TOPK_ARRIVE_STRIDE], 1u) == members - 1u)
+      l = atomicAdd(&st->done, 1u) == groups - 1u ? 1u : 0u;
+    last = l;
+  }
+  __syncthreads();
+  return last != 0u;
+}
+
+__device__ __forceinline__ uint32_t read_bin(const uint32_t *bin) {
+  return __hip_atomic_load(global(bin), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void clear_bin(uint32_t *bin) {
+  __hip_atomic_store(global(bin), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// By the last workgroup of a pass: the counters start the next pass at zero.
+__device__ __forceinline__ void reset_arrivals(TopkState *st) {
+  if (threadIdx.x < TOPK_ARRIVE_GROUPS) clear_bin(&st->arrive[threadIdx.x * TOPK_ARRIVE_STRIDE]);
+  if (threadIdx.x == 0) clear_bin(&st->done);
+}
+
+__device__ __forceinline__ void put_candidate(unsigned long long *c, unsigned long long v) {
+  __hip_atomic_store(global(c), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long get_candidate(const unsigned long long *c) {
+  return __hip_atomic_load(global(c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The job of this workgroup: blockIdx.y indexes the job table, or the single
@@ -69,57 +229,36 @@ __device__ __forceinline__ TopkJob job_of(const TopkJobs &J) {
   return load_uniform(J.jobs + blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void topk_init_kernel(TopkJobs J) {
-  const TopkJob job = job_of(J);
-  TopkState *st = job.st;
-  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) st->hist[b] = 0u;
-  if (threadIdx.x == 0) {
-    st->key_prefix = 0u;
-    st->need = job.kk;
-    st->idx_prefix = 0u;
-    st->idx_need = 0u;
-    st->tie_mode = 0u;
-    st->count = 0u;
-    st->eq_count = 0u;
-  }
-}
-
-__global__ __launch_bounds__(HIST_THREADS) void topk_hist_key_kernel(TopkJobs J, int pass) {
-  const TopkJob job = job_of(J);
-  if (job.kk == 0) return;
-  __shared__ uint32_t lh[TOPK_HIST];
-  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) lh[b] = 0u;
-  __syncthreads();
-  int shift, width;
-  key_digit(pass, &shift, &width);
-  const int hi = shift + width;
-  const uint32_t prefix = job.st->key_prefix;
-  const uint32_t mask = (1u << width) - 1u;
-  for_each_stat(job.stat, job.n, [&](int64_t, float v) {
-    const uint32_t k = order_key(v);
-    if (hi >= 32 || (k >> hi) == (prefix >> hi)) atomicAdd(&lh[(k >> shift) & mask], 1u);
-  });
-  flush_hist(lh, job.st->hist);
-}
-
-// One wave scans the histogram from the largest digit down (keys) or from the
-// smallest up (indices) and fixes the digit holding the need-th element.
+// Run by the whole last workgroup of a pass: move the merged histogram into
+// LDS (leaving the state's zero for the next pass), then one wave scans it from
+// the largest digit down (keys) or the smallest up (indices) and fixes the
+// digit that holds the need-th element.  `first`: the first pass of its kind
+// (its prefix starts empty; the first key pass needs kk elements); `last`: the
+// final key pass, which also sets up the tie passes and the compaction.
 template <bool KEYS>
-__global__ __launch_bounds__(64) void topk_select_kernel(TopkJobs J, int pass) {
-  const TopkJob job = job_of(J);
+__device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int width, bool first, bool last) {
   TopkState *st = job.st;
-  if (job.kk == 0) return;
-  if (!KEYS && st->tie_mode == 0u) return;
-  int shift, width;
-  if (KEYS) key_digit(pass, &shift, &width); else idx_digit(pass, &shift, &width);
   const int nb = 1 << width;
-  const int per = nb / 64;
+  // The whole table, without branches, so that the loads are in flight
+  // together: bins at and above nb are zero (no pass leaves a bin set).
+  constexpr int PER = TOPK_HIST / HIST_THREADS;
+  uint32_t h[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) h[m] = read_bin(&st->hist[threadIdx.x + m * HIST_THREADS]);
+#pragma unroll
+  for (int m = 0; m < PER; ++m) lh[threadIdx.x + m * HIST_THREADS] = h[m];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) clear_bin(&st->hist[threadIdx.x + m * HIST_THREADS]);
+  reset_arrivals(st);
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
+  const int per = (nb + 63) >> 6;
   // ordinal o = lane*per + i  <->  digit (KEYS ? nb-1-o : o)
   uint32_t mine = 0;
   for (int i = 0; i < per; ++i) {
     const int o = lane * per + i;
-    mine += st->hist[KEYS ? nb - 1 - o : o];
+    if (o < nb) mine += lh[KEYS ? nb - 1 - o : o];
   }
   uint32_t incl = mine;
   for (int off = 1; off < 64; off <<= 1) {
@@ -127,59 +266,104 @@ __global__ __launch_bounds__(64) void topk_select_kernel(TopkJobs J, int pass) {
     if (lane >= off) incl += t;
   }
   const uint32_t excl = incl - mine;
-  const uint32_t need = KEYS ? st->need : st->idx_need;
-  const bool owner = excl < need && need <= incl;
-  if (owner) {
-    uint32_t before = excl;
-    for (int i = 0; i < per; ++i) {
-      const int o = lane * per + i;
-      const int d = KEYS ? nb - 1 - o : o;
-      const uint32_t h = st->hist[d];
-      if (before + h >= need) {
-        const uint32_t left = need - before;
-        if (KEYS) {
-          st->key_prefix |= (uint32_t)d << shift;
-          st->need = left;
-          if (pass == 2) {
-            st->eq_count = h;
-            st->tie_mode = h > left ? 1u : 0u;
-            st->idx_need = left;
-          }
-        } else {
-          st->idx_prefix |= (uint32_t)d << shift;
+  const uint32_t need = KEYS ? (first ? job.kk : st->need) : st->idx_need;
+  if (!(excl < need && need <= incl)) return;
+  uint32_t before = excl;
+  for (int i = 0; i < per; ++i) {
+    const int o = lane * per + i;
+    const int d = KEYS ? nb - 1 - o : o;
+    const uint32_t h = lh[d];
+    if (before + h >= need) {
+      const uint32_t left = need - before;
+      if (KEYS) {
+        st->key_prefix = (first ? 0u : st->key_prefix) | ((uint32_t)d << shift);
+        st->need = left;
+        if (last) {
+          st->eq_count = h;
+          st->tie_mode = h > left ? 1u : 0u;
           st->idx_need = left;
+          st->count = 0u;
         }
-        break;
+      } else {
+        st->idx_prefix = (first ? 0u : st->idx_prefix) | ((uint32_t)d << shift);
+        st->idx_need = left;
       }
-      before += h;
+      return;
     }
+    before += h;
   }
-  __syncthreads();
-  for (int b = lane; b < nb; b += 64) st->hist[b] = 0u;
 }
 
-__global__ __launch_bounds__(HIST_THREADS) void topk_hist_idx_kernel(TopkJobs J, int pass) {
+// Key pass: histogram of digit [shift, shift+width) of the keys that match the
+// prefix found so far.
+__global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J, int shift, int width, int first,
+                                                                     int last) {
+  const TopkJob job = job_of(J);
+  if (job.kk == 0) return;
+  __shared__ uint32_t lh[TOPK_HIST];
+  const int nb = 1 << width;
+  clear_hist(lh, nb);
+  const int hi = shift + width;
+  const uint32_t prefix = first ? 0u : job.st->key_prefix;
+  const uint32_t mask = (uint32_t)nb - 1u;
+  if (first) {
+    first_digit_hist(job.stat, job.n, lh, shift, mask);
+  } else {
+    for_each_stat(job.stat, job.n, [&](int64_t, float v) {
+      const uint32_t k = order_key(v);
+      hist_add<false>(lh, (k >> shift) & mask, (k >> hi) == (prefix >> hi));
+    });
+  }
+  flush_hist(lh, job.st->hist, nb);
+  if (last_to_finish(job.st)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
+}
+
+// Index pass: among keys equal to the threshold, histogram of index digit
+// [shift, shift+width) of the indices that match the index prefix so far.
+__global__ __launch_bounds__(HIST_THREADS) void topk_index_pass_kernel(TopkJobs J, int shift, int width, int first) {
   const TopkJob job = job_of(J);
   if (job.kk == 0 || job.st->tie_mode == 0u) return;
   __shared__ uint32_t lh[TOPK_HIST];
-  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) lh[b] = 0u;
-  __syncthreads();
-  int shift, width;
-  idx_digit(pass, &shift, &width);
+  const int nb = 1 << width;
+  clear_hist(lh, nb);
   const int hi = shift + width;
   const uint32_t key = job.st->key_prefix;
-  const uint32_t prefix = job.st->idx_prefix;
-  const uint32_t mask = (1u << width) - 1u;
+  const uint32_t prefix = first ? 0u : job.st->idx_prefix;
+  const uint32_t mask = (uint32_t)nb - 1u;
   for_each_stat(job.stat, job.n, [&](int64_t i, float v) {
     const uint32_t u = (uint32_t)i;
-    if (order_key(v) == key && (hi >= 31 || (u >> hi) == (prefix >> hi))) atomicAdd(&lh[(u >> shift) & mask], 1u);
+    hist_add<true>(lh, (u >> shift) & mask, order_key(v) == key && (hi >= 32 || (u >> hi) == (prefix >> hi)));
   });
-  flush_hist(lh, job.st->hist);
+  flush_hist(lh, job.st->hist, nb);
+  if (last_to_finish(job.st)) select_digit<false>(job, lh, shift, width, first != 0, false);
 }
 
+// Outputs from sorted candidates (or none): positions past kk get -inf / -1.
+__device__ __forceinline__ void write_results(const TopkJob &job, const unsigned long long *s) {
+  const int kk = (int)job.kk;
+  for (int i = threadIdx.x; i < job.top_k; i += blockDim.x) {
+    if (i < kk) {
+      const unsigned long long c = s[i];
+      job.vals[i] = key_value((uint32_t)(c >> 32));
+      job.idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
+    } else {
+      job.vals[i] = -__builtin_inff();
+      job.idx[i] = -1;
+    }
+  }
+}
+
+// Compaction: every element above the threshold, and those equal to it that
+// are needed (all, or those with index <= the index threshold), go to the
+// candidate list; the last workgroup sorts the kk candidates (descending key,
+// then ascending index, both encoded in one 64-bit word) and writes the outputs.
 __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) {
   const TopkJob job = job_of(J);
-  if (job.kk == 0) return;
+  __shared__ unsigned long long s[EMRI_MAX_TOPK];
+  if (job.kk == 0) {
+    if (blockIdx.x == 0) write_results(job, s);
+    return;
+  }
   TopkState *st = job.st;
   const uint32_t key = st->key_prefix;
   const bool tie = st->tie_mode != 0u;
@@ -191,20 +375,66 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
     const bool sel = k > key || (k == key && (!tie || (uint32_t)i <= thr));
     if (sel) {
       const uint32_t pos = atomicAdd(&st->count, 1u);
-      if (pos < kk) cand[pos] = ((unsigned long long)k << 32) | (unsigned long long)(0xffffffffu - (uint32_t)i);
+      if (pos < kk) put_candidate(cand + pos, ((unsigned long long)k << 32) | (0xffffffffu - (uint32_t)i));
     }
   });
-}
-
-__global__ __launch_bounds__(1024) void topk_final_kernel(TopkJobs J) {
-  const TopkJob job = job_of(J);
-  __shared__ unsigned long long s[EMRI_MAX_TOPK];
-  const int kk = (int)job.kk;
-  int p2 = 1;
-  while (p2 < kk) p2 <<= 1;
-  for (int i = threadIdx.x; i < p2; i += blockDim.x) s[i] = i < kk ? job.cand[i] : 0ull;
+  if (!last_to_finish(st)) return;
+  reset_arrivals(st);
+  const int nc = (int)kk;
+  {
+    constexpr int PER = EMRI_MAX_TOPK / HIST_THREADS;
+    unsigned long long c[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int i = threadIdx.x + m * HIST_THREADS;
+      c[m] = get_candidate(cand + (i < nc ? i : nc - 1));        // in bounds, no branch
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int i = threadIdx.x + m * HIST_THREADS;
+      if (i < nc) s[i] = c[m];
+    }
+  }
   __syncthreads();
-  // bitonic sort, descending
+  if (nc <= RANK_SORT_MAX) {
+    // the words are distinct: a word's place is the number of larger words
+    constexpr int M = RANK_SORT_MAX / HIST_THREADS;
+    unsigned long long w[M];
+    int rank[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int i = threadIdx.x + m * HIST_THREADS;
+      w[m] = i < nc ? s[i] : ~0ull;
+      rank[m] = 0;
+    }
+    // zero words (below every candidate) pad the list to a multiple of 8
+    if (threadIdx.x < 8 && nc + threadIdx.x < EMRI_MAX_TOPK) s[nc + threadIdx.x] = 0ull;
+    __syncthreads();
+#pragma unroll 8
+    for (int j = 0; j < ((nc + 7) & ~7); ++j) {
+      const unsigned long long o = s[j];
+#pragma unroll
+      for (int m = 0; m < M; ++m) rank[m] += o > w[m] ? 1 : 0;
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int i = threadIdx.x + m * HIST_THREADS;
+      if (i < nc) {
+        job.vals[rank[m]] = key_value((uint32_t)(w[m] >> 32));
+        job.idx[rank[m]] = (int64_t)(0xffffffffu - (uint32_t)(w[m] & 0xffffffffull));
+      }
+    }
+    for (int i = nc + threadIdx.x; i < job.top_k; i += blockDim.x) {
+      job.vals[i] = -__builtin_inff();
+      job.idx[i] = -1;
+    }
+    return;
+  }
+  // bitonic network, descending, over the next power of two
+  int p2 = 1;
+  while (p2 < nc) p2 <<= 1;
+  for (int i = nc + threadIdx.x; i < p2; i += blockDim.x) s[i] = 0ull;
+  __syncthreads();
   for (int size = 2; size <= p2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < p2; i += blockDim.x) {
@@ -221,16 +451,7 @@ __global__ __launch_bounds__(1024) void topk_final_kernel(TopkJobs J) {
       __syncthreads();
     }
   }
-  for (int i = threadIdx.x; i < job.top_k; i += blockDim.x) {
-    if (i < kk) {
-      const unsigned long long c = s[i];
-      job.vals[i] = key_value((uint32_t)(c >> 32));
-      job.idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
-    } else {
-      job.vals[i] = -__builtin_inff();
-      job.idx[i] = -1;
-    }
-  }
+  write_results(job, s);
 }
 
 }  // namespace
@@ -256,18 +477,19 @@ hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu
   if (n_jobs <= 0) return hipSuccess;
   const int64_t work = (max_n + 4 * HIST_THREADS - 1) / (4 * HIST_THREADS);
   const int gx = (int)(work < (int64_t)cu_count * 4 ? (work > 0 ? work : 1) : (int64_t)cu_count * 4);
-  const dim3 one(1, n_jobs), hist(gx, n_jobs);
-  hipLaunchKernelGGL(topk_init_kernel, one, dim3(256), 0, stream, J);
-  for (int pass = 0; pass < 3; ++pass) {
-    hipLaunchKernelGGL(topk_hist_key_kernel, hist, dim3(HIST_THREADS), 0, stream, J, pass);
-    hipLaunchKernelGGL(topk_select_kernel<true>, one, dim3(64), 0, stream, J, pass);
+  const dim3 grid(gx, n_jobs), block(HIST_THREADS);
+  static const int key_shift[3] = {21, 10, 0}, key_width[3] = {11, 11, 10};
+  for (int pass = 0; pass < 3; ++pass)
+    hipLaunchKernelGGL(topk_key_pass_kernel, grid, block, 0, stream, J, key_shift[pass], key_width[pass],
+                       pass == 0 ? 1 : 0, pass == 2 ? 1 : 0);
+  // index digits cover the bits of the largest index, top digit first
+  int bits = 1;
+  while (bits < 31 && ((int64_t)1 << bits) < max_n) ++bits;
+  for (int hi = bits; hi > 0; hi -= INDEX_DIGIT) {
+    const int width = hi < INDEX_DIGIT ? hi : INDEX_DIGIT;
+    hipLaunchKernelGGL(topk_index_pass_kernel, grid, block, 0, stream, J, hi - width, width, hi == bits ? 1 : 0);
   }
-  for (int pass = 0; pass < 3; ++pass) {
-    hipLaunchKernelGGL(topk_hist_idx_kernel, hist, dim3(HIST_THREADS), 0, stream, J, pass);
-    hipLaunchKernelGGL(topk_select_kernel<false>, one, dim3(64), 0, stream, J, pass);
-  }
-  hipLaunchKernelGGL(topk_compact_kernel, hist, dim3(HIST_THREADS), 0, stream, J);
-  hipLaunchKernelGGL(topk_final_kernel, one, dim3(1024), 0, stream, J);
+  hipLaunchKernelGGL(topk_compact_kernel, grid, block, 0, stream, J);
   return hipGetLastError();
 }
 

@@ -297,6 +297,50 @@ def test_topk_ties_and_padding(gpu_lib):
     assert none["stat"].shape == (100,)
 
 
+@pytest.mark.parametrize("n,k,rare", [(3_000_000, 4096, False), (3_000_000, 4096, True), (1_234_567, 777, True),
+                                       (4097, 4096, False), (70_000, 1, True)])
+def test_topk_massive_ties(gpu_lib, n, k, rare):
+    """Three distinct statistic values over up to 3e6 templates: the k-th value is
+    shared by far more templates than are needed, so the index passes decide
+    (over two index digits at 3e6), and equal keys fill whole waves.  `rare`:
+    the two larger values are rare, so the cut falls among the ties of the
+    smallest value, below elements that are all taken."""
+    n_seg, n_bins, t = 1, 64, 1.0
+    P = np.ones((n_seg, n_bins))
+    P[0, 3], P[0, 7] = 5.0, 4.0
+    g = np.random.default_rng(n + k)
+    if rare:
+        c = np.where(g.random(n) < 5e-4, 3, np.where(g.random(n) < 5e-4, 7, g.integers(8, 64, n)))
+    else:
+        c = g.integers(0, 64, n)
+    C = c.astype(np.float32)[:, None]                  # position = bin, exactly
+    gpu = score_gpu(gpu_lib, P, np.zeros(n_seg), np.ones((n_seg, 1)), C, t, k)
+    assert np.array_equal(gpu["stat"], P[0, c].astype(np.float32))
+    ov, oi = oracle.topk_order(P[0, c], k)
+    assert np.array_equal(gpu["topk_idx"], oi)
+    assert np.array_equal(gpu["topk_val"], ov.astype(np.float32))
+
+
+@pytest.mark.parametrize("sigma,k", [(3.0, 256), (0.05, 4096), (0.05, 1000)])
+def test_topk_of_wide_and_narrow_statistics(gpu_lib, sigma, k):
+    """2e6 templates whose statistics span many binades (lognormal sigma 3: the
+    leading key digit takes many values) or one (sigma 0.05: a few values of the
+    leading digit hold everything).  The selection must be exactly the first k
+    of the statistic the GPU returned, ordered by (-S, index)."""
+    g = np.random.default_rng(int(sigma * 100) + k)
+    n_seg, n_bins, t, n = 3, 4096, 1.0, 2_000_000
+    P = np.exp(g.normal(0.0, sigma, (n_seg, n_bins)))
+    if sigma > 1:
+        P[:, ::7] *= -1.0                                # negative values too
+    f0 = np.array([100.0, 900.0, 2000.0])
+    U = g.uniform(-1.0, 1.0, (n_seg, 2)) * 400.0
+    C = g.uniform(-2.0, 2.0, (n, 2)).astype(np.float32)
+    gpu = score_gpu(gpu_lib, P, f0, U, C, t, k)
+    ov, oi = oracle.topk_order(gpu["stat"].astype(np.float64), k)
+    assert np.array_equal(gpu["topk_idx"], oi)
+    assert np.array_equal(gpu["topk_val"], ov.astype(np.float32))
+
+
 def test_topk_nan_and_negative(gpu_lib):
     n_seg, n_bins, t = 2, 8, 1.0
     P = np.array([[1, -3, np.nan, 0, 2, 5, -0.0, 4], [0, 0, 0, 0, 0, 0, 0, 0]], dtype=np.float64)
