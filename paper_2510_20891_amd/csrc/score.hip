@@ -281,21 +281,21 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_validate_kernel(ScorePara
 
 // Per-segment constants f0*T, U*T (FP64) and the bounds of the wild-template
 // test: bound[0] = max |f0 T|, bound[1+k] = max_alpha |U[alpha,k] T| (+inf if
-// an entry is not finite).  Also clears the near-tie counter and resets the
-// top-k state of the call.  One workgroup of 256 threads.
+// an entry is not finite).  Also clears the near-tie counter and, with
+// reset_topk, the top-k state of the call.  One workgroup of 256 threads.
 __device__ __forceinline__ double abs_bound(double v) {
   const double av = __builtin_fabs(v);
   return av <= 1.7976931348623157e308 ? av : __builtin_inf();     // NaN and inf: +inf
 }
 
-__device__ __forceinline__ void prep_one(const PrepJob &job) {
+__device__ __forceinline__ void prep_one(const PrepJob &job, bool reset_topk) {
   __shared__ double red[4][EMRI_MAX_K + 1];
   const double *f0 = job.f0, *U = job.U;
   const int K = job.K, n_seg = job.n_seg, stride = job.seg_stride;
   const double t_sft = job.t_sft;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0 && job.near_tie) *job.near_tie = 0ull;
-  if (job.topk) topk_state_reset(job.topk);
+  if (job.topk && reset_topk) topk_state_reset(job.topk, 0, 1);
   for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
     job.seg[(size_t)a * stride] = f0[a] * t_sft;
     for (int k = 0; k < K; ++k) job.seg[(size_t)a * stride + 1 + k] = U[(size_t)a * K + k] * t_sft;
@@ -353,11 +353,21 @@ __device__ __forceinline__ void prep_one(const PrepJob &job) {
   }
 }
 
-__global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) { prep_one(job); }
+// Workgroup 0 computes the constants; any others reset a share of the top-k
+// state each, at the same time.
+constexpr int PREP_RESET_PARTS = 8;
+
+__global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) {
+  if (blockIdx.x > 0) {
+    topk_state_reset(job.topk, blockIdx.x - 1, gridDim.x - 1);
+    return;
+  }
+  prep_one(job, false);
+}
 
 __global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs, int *counter) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;     // work-item counter of the scoring launch
-  prep_one(load_uniform(jobs + blockIdx.x));
+  prep_one(load_uniform(jobs + blockIdx.x), true);
 }
 
 // Templates per lane: as many FMA chains as the 256 VGPRs of two waves per SIMD
@@ -441,7 +451,7 @@ int score_templates_per_lane(int K, bool alt) {
 }
 
 hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream) {
-  hipLaunchKernelGGL(score_prep_kernel, dim3(1), dim3(256), 0, stream, job);
+  hipLaunchKernelGGL(score_prep_kernel, dim3(job.topk ? 1 + PREP_RESET_PARTS : 1), dim3(256), 0, stream, job);
   return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace emri {
@@ -124,12 +125,12 @@ int mixed_templates_per_lane(int K);
 hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream);
 hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream);
 
-// Top-k state of one job.  Only hist, arrive and done (all zero) must hold
-// before the first pass: topk_state_reset, run by the prep kernels ahead of the
-// scores, sets them, and every pass leaves them so again; the other fields are
-// written by the passes before they are read.
-constexpr int TOPK_ARRIVE_GROUPS = 32;   // arrival counters per pass (one per 32nd of the workgroups)
-constexpr int TOPK_ARRIVE_STRIDE = 32;   // words between counters: one 128-byte line each
+// Top-k state of one job.  The histograms and counters must be zero before
+// the first pass: topk_state_reset, run by the prep kernels ahead of the
+// scores, clears them, and every pass leaves them so again; the other fields
+// are written by the passes before they are read.
+constexpr int TOPK_GROUPS = 8;           // workgroup b of a pass belongs to group b mod 8
+constexpr int TOPK_ARRIVE_STRIDE = 32;   // words between arrival counters: one 128-byte line each
 
 struct TopkState {
   uint32_t key_prefix;        // bits of the k-th largest key found so far
@@ -139,17 +140,20 @@ struct TopkState {
   uint32_t tie_mode;          // 1: keys equal to the threshold are cut by index
   uint32_t count;             // compaction cursor
   uint32_t eq_count;          // number of keys equal to the threshold
-  uint32_t done;              // groups of workgroups of the current pass that have finished
+  uint32_t done;              // groups of the current pass that have finished
   uint32_t pad[24];
-  uint32_t arrive[TOPK_ARRIVE_GROUPS * TOPK_ARRIVE_STRIDE];   // finished workgroups per group
-  uint32_t hist[TOPK_HIST];
+  uint32_t arrive[TOPK_GROUPS * TOPK_ARRIVE_STRIDE];   // finished workgroups of each group
+  uint32_t hist[TOPK_HIST];                          // histogram of the pass, all groups
+  uint32_t ghist[TOPK_GROUPS][TOPK_HIST];            // histogram of the pass, one group
 };
 
-// Called by every thread of one workgroup.
-__device__ __forceinline__ void topk_state_reset(TopkState *st) {
-  for (int b = threadIdx.x; b < TOPK_HIST; b += blockDim.x) st->hist[b] = 0u;
-  for (int g = threadIdx.x; g < TOPK_ARRIVE_GROUPS; g += blockDim.x) st->arrive[g * TOPK_ARRIVE_STRIDE] = 0u;
-  if (threadIdx.x == 0) st->done = 0u;
+// Part `part` of `parts` of the reset; called by every thread of a workgroup.
+__device__ __forceinline__ void topk_state_reset(TopkState *st, int part, int parts) {
+  constexpr int words = (int)((sizeof(TopkState) - offsetof(TopkState, arrive)) / sizeof(uint32_t));
+  uint32_t *z = st->arrive;          // arrive, hist and ghist are contiguous
+  const int lo = words * part / parts, hi = words * (part + 1) / parts;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) z[i] = 0u;
+  if (part == 0 && threadIdx.x == 0) st->done = 0u;
 }
 
 // One top-k problem: the statistic, its length, and where state and results live.

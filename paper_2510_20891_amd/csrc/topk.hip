@@ -3,17 +3,17 @@
 // template index; NaN ranks below every number and -0 equals +0.
 //
 // Radix select on an order-preserving 32-bit key of S: three histogram passes
-// (11, 11 and 10 bits) find the key T of the k-th element and how many of the
+// (12, 10 and 10 bits) find the key T of the k-th element and how many of the
 // elements equal to T belong to the top-k.  If T is shared by more elements
 // than are needed, index passes (digits of at most 12 bits over the bits an
 // index of this length has) select the needed count of smallest template
 // indices among them; otherwise they return at once.  One compaction pass then
-// gathers exactly k (key, index) pairs and sorts them with a bitonic network in
-// LDS.  Every pass streams the statistic with 16-byte loads and builds its
-// histogram in LDS, merged with one atomic per non-empty bin per workgroup.
-// The last workgroup of a pass to finish (an arrival counter in the state; no
-// workgroup ever waits for another) picks the digit for the next pass, or, in
-// the compaction pass, sorts the candidates, so a top-k is 4 to 7 launches.
+// gathers exactly k (key, index) pairs and orders them.  Every pass streams
+// the statistic with 16-byte loads and builds its histogram in LDS; the
+// histograms of all workgroups are merged in two levels, and the last
+// workgroup of a pass to finish (arrival counters in the state; no workgroup
+// ever waits for another) picks the digit for the next pass or, in the
+// compaction pass, orders the winners, so a top-k is 4 to 7 launches.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -98,16 +98,34 @@ __device__ __forceinline__ void hist_add(uint32_t *lh, uint32_t bin, bool in) {
   atomicAdd(&lh[bin], 1u);
 }
 
-// Histogram of the first key digit (sign, exponent and two mantissa bits).
+// Histogram of the first key digit (sign, exponent and three mantissa bits).
 // Across a statistic vector it takes a few neighbouring values, so an LDS
 // atomic per element would serialise on them.  Each thread counts the 8 bins
 // of its wave's window (starting 3 below the bin of the wave's first element)
-// in 8-bit fields of one 64-bit register, over the 4 * STREAM elements of one
-// group of loads; then the wave adds the fields up (16 bits each: at most 64 x
-// 16 per bin) and one lane adds the 8 sums to the LDS histogram.  Elements
-// outside the window are counted one by one.  Every lane of a wave runs the
-// same number of groups (those the wave's first lane runs), so the wave-wide
-// sums see all 64 lanes.
+// in 8-bit fields of one 64-bit register, without branches; a group of loads
+// with an element outside the window counts those elements one by one.  After
+// at most 15 groups (240 elements per field) and at the end, the wave adds the
+// fields up (16 bits each: at most 64 x 240 per bin) and one lane adds the 8
+// sums to the LDS histogram.  Every lane of a wave runs the same number of
+// groups (those the wave's first lane runs), so the wave-wide sums see all 64
+// lanes; lanes past the end load the last element again and count nothing.
+__device__ __forceinline__ void add_window(uint32_t *lh, uint32_t base, uint64_t packed) {
+  unsigned long long even = packed & 0x00ff00ff00ff00ffull;          // bins base+0, +2, +4, +6
+  unsigned long long odd = (packed >> 8) & 0x00ff00ff00ff00ffull;    // bins base+1, +3, +5, +7
+  for (int off = 32; off > 0; off >>= 1) {
+    even += __shfl_xor(even, off, 64);
+    odd += __shfl_xor(odd, off, 64);
+  }
+  if (__lane_id() == 0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const uint32_t ce = (uint32_t)(even >> (16 * f)) & 0xffffu, co = (uint32_t)(odd >> (16 * f)) & 0xffffu;
+      if (ce) atomicAdd(&lh[base + 2 * f], ce);
+      if (co) atomicAdd(&lh[base + 2 * f + 1], co);
+    }
+  }
+}
+
 __device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, uint32_t *lh, int shift, uint32_t mask) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   const gmem<const f4> *s4 = global(reinterpret_cast<const f4 *>(stat));
@@ -115,47 +133,46 @@ __device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, u
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int lane = (int)__lane_id();
   uint32_t base = 0u;
-  bool have_base = false;
+  uint64_t packed = 0ull;
+  int groups = 0;
   for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 - lane < n4; q0 += STREAM * stride) {
     f4 v[STREAM];
 #pragma unroll
     for (int u = 0; u < STREAM; ++u) {
       const int64_t q = q0 + u * stride;
-      v[u] = q < n4 ? s4[q] : f4{0.f, 0.f, 0.f, 0.f};
+      v[u] = s4[q < n4 ? q : n4 - 1];
     }
-    if (!have_base) {                // the wave's first lane has an element here
+    if (groups == 0) {                // the wave's first lane has an element here
       const uint32_t b0 = __builtin_amdgcn_readfirstlane((order_key(v[0].x) >> shift) & mask);
       base = b0 >= 3u ? b0 - 3u : 0u;
-      have_base = true;
     }
-    uint64_t packed = 0ull;
+    bool miss = false;
 #pragma unroll
     for (int u = 0; u < STREAM; ++u) {
-      if (q0 + u * stride < n4) {
+      const bool live = q0 + u * stride < n4;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const uint32_t d = ((order_key(v[u][c]) >> shift) & mask) - base;
+        packed += (live && d < 8u) ? 1ull << (8u * d) : 0ull;
+        miss |= live && d >= 8u;
+      }
+    }
+    if (miss) {
+#pragma unroll
+      for (int u = 0; u < STREAM; ++u) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const uint32_t bin = (order_key(v[u][c]) >> shift) & mask;
-          const uint32_t d = bin - base;
-          if (d < 8u) packed += 1ull << (8u * d);
-          else atomicAdd(&lh[bin], 1u);
+          if (q0 + u * stride < n4 && bin - base >= 8u) atomicAdd(&lh[bin], 1u);
         }
       }
     }
-    unsigned long long even = packed & 0x00ff00ff00ff00ffull;          // bins base+0, +2, +4, +6
-    unsigned long long odd = (packed >> 8) & 0x00ff00ff00ff00ffull;    // bins base+1, +3, +5, +7
-    for (int off = 32; off > 0; off >>= 1) {
-      even += __shfl_xor(even, off, 64);
-      odd += __shfl_xor(odd, off, 64);
-    }
-    if (lane == 0) {
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const uint32_t ce = (uint32_t)(even >> (16 * f)) & 0xffffu, co = (uint32_t)(odd >> (16 * f)) & 0xffffu;
-        if (ce) atomicAdd(&lh[base + 2 * f], ce);
-        if (co) atomicAdd(&lh[base + 2 * f + 1], co);
-      }
+    if (++groups % 15 == 0) {
+      add_window(lh, base, packed);
+      packed = 0ull;
     }
   }
+  if (groups % 15 != 0) add_window(lh, base, packed);
   for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     atomicAdd(&lh[(order_key(stat[i]) >> shift) & mask], 1u);
 }
@@ -165,39 +182,70 @@ __device__ __forceinline__ void clear_hist(uint32_t *lh, int nb) {
   __syncthreads();
 }
 
+// A group histogram keeps bin b at word (b mod 8) * (TOPK_HIST / 8) + b / 8,
+// so neighbouring bins, which the leading digit fills at once, sit on
+// different cache lines and their atomics are not serialised together.
+constexpr int GH_ROWS = 8, GH_COLS = TOPK_HIST / GH_ROWS;
+__device__ __forceinline__ int gh_word(int b) { return (b % GH_ROWS) * GH_COLS + b / GH_ROWS; }
+__device__ __forceinline__ int gh_bin(int w) { return (w % GH_COLS) * GH_ROWS + w / GH_COLS; }
+
 __device__ __forceinline__ void flush_hist(const uint32_t *lh, uint32_t *gh, int nb) {
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    if (lh[b]) atomicAdd(&gh[b], lh[b]);
+    if (lh[b]) atomicAdd(&gh[gh_word(b)], lh[b]);
 }
 
-// Everything one workgroup leaves for the last one of its pass goes through
-// agent-scope atomics, which are coherent across the chip's L2 caches without
-// cache maintenance: histogram bins and counters by read-modify-write; the
-// merged bins and the candidates by atomic loads and stores.  A workgroup
-// waits until its own atomics have completed (vmcnt), then counts itself on
-// its group's arrival counter (workgroup b is in group b mod 32); the last of
-// a group counts the group on `done`, and the workgroup that completes `done`
-// reads after that, so it sees every other workgroup's completed atomics.
-// The two levels keep any one counter to 32 arrivals: atomics on one address
-// are serialised, and all workgroups of a pass finish at about the same time.
-// No workgroup waits for another, and no pass writes back or invalidates an L2
+// Everything one workgroup leaves for another goes through agent-scope
+// atomics, which are coherent across the chip's L2 caches without cache
+// maintenance: histogram bins and counters by read-modify-write, merged bins
+// and candidates by atomic loads and stores.  A pass merges in two levels, so
+// that no address takes more than about 128 atomics (atomics on one address
+// are serialised, and the workgroups of a pass finish at about the same time):
+// a workgroup adds its LDS histogram into its group's histogram, waits until
+// its atomics have completed (vmcnt) and counts itself on the group's arrival
+// counter; the last of a group moves the group histogram into the pass
+// histogram, waits, and counts the group on `done`; the workgroup that
+// completes `done` sees every other workgroup's completed atomics.  No
+// workgroup waits for another, and no pass writes back or invalidates an L2
 // cache (an agent-scope fence would, once per workgroup).
-__device__ __forceinline__ bool last_to_finish(TopkState *st) {
-  __shared__ uint32_t last;
+__device__ __forceinline__ uint32_t read_bin(const uint32_t *bin);
+__device__ __forceinline__ void clear_bin(uint32_t *bin);
+
+__device__ __forceinline__ bool finish_pass(TopkState *st, int nb) {
+  __shared__ uint32_t flag;
+  const uint32_t G = TOPK_GROUPS, g = blockIdx.x % G;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t G = TOPK_ARRIVE_GROUPS, g = blockIdx.x % G;
-    const uint32_t members = (gridDim.x - g + G - 1) / G;      // workgroups b < gridDim.x with b mod G == g
-    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
-    uint32_t l = 0u;
-    if (atomicAdd(&st->arrive[g * TOPK_ARRIVE_STRIDE], 1u) == members - 1u)
-      l = atomicAdd(&st->done, 1u) == groups - 1u ? 1u : 0u;
-    last = l;
+    const uint32_t members = (gridDim.x - g + G - 1) / G;     // workgroups b < gridDim.x with b mod G == g
+    flag = atomicAdd(&st->arrive[g * TOPK_ARRIVE_STRIDE], 1u) == members - 1u ? 1u : 0u;
   }
   __syncthreads();
-  return last != 0u;
+  if (flag == 0u) return false;
+  if (nb > 0) {
+    // all loads first (no branches between them), then the adds and clears
+    constexpr int PER = TOPK_HIST / HIST_THREADS;
+    uint32_t h[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) h[m] = read_bin(&st->ghist[g][threadIdx.x + m * HIST_THREADS]);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int w = threadIdx.x + m * HIST_THREADS;
+      if (h[m]) {
+        atomicAdd(&st->hist[gh_bin(w)], h[m]);
+        clear_bin(&st->ghist[g][w]);
+      }
+    }
+  }
+  if (threadIdx.x == 0) clear_bin(&st->arrive[g * TOPK_ARRIVE_STRIDE]);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
+    flag = atomicAdd(&st->done, 1u) == groups - 1u ? 1u : 0u;
+  }
+  __syncthreads();
+  return flag != 0u;
 }
 
 __device__ __forceinline__ uint32_t read_bin(const uint32_t *bin) {
@@ -206,12 +254,6 @@ __device__ __forceinline__ uint32_t read_bin(const uint32_t *bin) {
 
 __device__ __forceinline__ void clear_bin(uint32_t *bin) {
   __hip_atomic_store(global(bin), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// By the last workgroup of a pass: the counters start the next pass at zero.
-__device__ __forceinline__ void reset_arrivals(TopkState *st) {
-  if (threadIdx.x < TOPK_ARRIVE_GROUPS) clear_bin(&st->arrive[threadIdx.x * TOPK_ARRIVE_STRIDE]);
-  if (threadIdx.x == 0) clear_bin(&st->done);
 }
 
 __device__ __forceinline__ void put_candidate(unsigned long long *c, unsigned long long v) {
@@ -249,7 +291,7 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
   for (int m = 0; m < PER; ++m) lh[threadIdx.x + m * HIST_THREADS] = h[m];
 #pragma unroll
   for (int m = 0; m < PER; ++m) clear_bin(&st->hist[threadIdx.x + m * HIST_THREADS]);
-  reset_arrivals(st);
+  if (threadIdx.x == 0) clear_bin(&st->done);
   __syncthreads();
   if (threadIdx.x >= 64) return;
   const int lane = threadIdx.x;
@@ -314,8 +356,8 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J,
       hist_add<false>(lh, (k >> shift) & mask, (k >> hi) == (prefix >> hi));
     });
   }
-  flush_hist(lh, job.st->hist, nb);
-  if (last_to_finish(job.st)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
+  flush_hist(lh, job.st->ghist[blockIdx.x % TOPK_GROUPS], nb);
+  if (finish_pass(job.st, nb)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
 }
 
 // Index pass: among keys equal to the threshold, histogram of index digit
@@ -334,8 +376,8 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_index_pass_kernel(TopkJobs 
     const uint32_t u = (uint32_t)i;
     hist_add<true>(lh, (u >> shift) & mask, order_key(v) == key && (hi >= 32 || (u >> hi) == (prefix >> hi)));
   });
-  flush_hist(lh, job.st->hist, nb);
-  if (last_to_finish(job.st)) select_digit<false>(job, lh, shift, width, first != 0, false);
+  flush_hist(lh, job.st->ghist[blockIdx.x % TOPK_GROUPS], nb);
+  if (finish_pass(job.st, nb)) select_digit<false>(job, lh, shift, width, first != 0, false);
 }
 
 // Outputs from sorted candidates (or none): positions past kk get -inf / -1.
@@ -378,8 +420,8 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
       if (pos < kk) put_candidate(cand + pos, ((unsigned long long)k << 32) | (0xffffffffu - (uint32_t)i));
     }
   });
-  if (!last_to_finish(st)) return;
-  reset_arrivals(st);
+  if (!finish_pass(st, 0)) return;
+  if (threadIdx.x == 0) clear_bin(&st->done);
   const int nc = (int)kk;
   {
     constexpr int PER = EMRI_MAX_TOPK / HIST_THREADS;
@@ -478,7 +520,7 @@ hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu
   const int64_t work = (max_n + 4 * HIST_THREADS - 1) / (4 * HIST_THREADS);
   const int gx = (int)(work < (int64_t)cu_count * 4 ? (work > 0 ? work : 1) : (int64_t)cu_count * 4);
   const dim3 grid(gx, n_jobs), block(HIST_THREADS);
-  static const int key_shift[3] = {21, 10, 0}, key_width[3] = {11, 11, 10};
+  static const int key_shift[3] = {20, 10, 0}, key_width[3] = {12, 10, 10};
   for (int pass = 0; pass < 3; ++pass)
     hipLaunchKernelGGL(topk_key_pass_kernel, grid, block, 0, stream, J, key_shift[pass], key_width[pass],
                        pass == 0 ? 1 : 0, pass == 2 ? 1 : 0);
