@@ -29,6 +29,8 @@ struct PlanData {
   BatchLaunch launch;
   const PrepJob *prep_jobs;
   const TopkJob *topk_jobs;
+  const int32_t *topk_block_job;
+  int64_t topk_blocks;
   int32_t n_items;
   int32_t has_work;
 };
@@ -64,7 +66,7 @@ int check_problem(const emri_problem &pb, int i, int K, int dtype) {
 
 // Workspace layout of a batch.
 struct Layout {
-  size_t params, prep, topk_jobs, items, counter, seg, bound, stat, topk, total;
+  size_t params, prep, topk_jobs, topk_blocks, items, counter, seg, bound, stat, topk, total;
   std::vector<size_t> seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off;
 };
 
@@ -81,6 +83,10 @@ Layout make_layout(const emri_problem *pbs, int n, int K, int64_t max_items) {
   L.params = take(sizeof(ScoreParams) * n);
   L.prep = take(sizeof(PrepJob) * n);
   L.topk_jobs = take(sizeof(TopkJob) * n);
+  std::vector<int64_t> topk_n;
+  for (int i = 0; i < n; ++i)
+    if (pbs[i].top_k > 0) topk_n.push_back(pbs[i].n_tmpl);
+  L.topk_blocks = take(sizeof(int32_t) * (size_t)topk_max_blocks(topk_n.data(), (int)topk_n.size()));
   L.items = take(sizeof(BatchItem) * (size_t)max_items);
   L.counter = take(sizeof(int));
   L.seg = off;
@@ -301,7 +307,12 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   };
   copy(L.params, params.data(), sizeof(ScoreParams) * params.size());
   copy(L.prep, preps.data(), sizeof(PrepJob) * preps.size());
+  const int64_t topk_blocks = topk_assign_blocks(topks.data(), (int)topks.size(), cus);
+  std::vector<int32_t> block_job((size_t)topk_blocks);
+  for (size_t j = 0; j < topks.size(); ++j)
+    for (int b = 0; b < topks[j].nblk; ++b) block_job[(size_t)topks[j].first_block + b] = (int32_t)j;
   copy(L.topk_jobs, topks.data(), sizeof(TopkJob) * topks.size());
+  copy(L.topk_blocks, block_job.data(), sizeof(int32_t) * block_job.size());
   copy(L.items, items.data(), sizeof(BatchItem) * items.size());
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched plan copies: %s", hipGetErrorString(err));
 
@@ -323,6 +334,8 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.launch.mixed = mixed ? 1 : 0;
   pd.prep_jobs = reinterpret_cast<const PrepJob *>(ws + L.prep);
   pd.topk_jobs = reinterpret_cast<const TopkJob *>(ws + L.topk_jobs);
+  pd.topk_block_job = reinterpret_cast<const int32_t *>(ws + L.topk_blocks);
+  pd.topk_blocks = topk_blocks;
   pd.n_items = (int)items.size();
   pd.has_work = items.empty() ? 0 : 1;
   std::memset(plan, 0, sizeof *plan);
@@ -344,7 +357,8 @@ extern "C" int score_batched_run(const emri_batch_plan *plan, void *hip_stream) 
     TopkJobs J;
     std::memset(&J, 0, sizeof J);
     J.jobs = pd.topk_jobs;
-    err = launch_topk_jobs(J, pd.n_topk, pd.max_topk_n, pd.cus, stream);
+    J.block_job = pd.topk_block_job;
+    err = launch_topk_jobs(J, pd.topk_blocks, pd.max_topk_n, stream);
   }
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched launch: %s", hipGetErrorString(err));
   return EMRI_OK;

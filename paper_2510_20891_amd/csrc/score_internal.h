@@ -166,17 +166,25 @@ struct TopkJob {
   unsigned long long *cand;    // kk candidate (key, index) pairs
   float *vals;
   int64_t *idx;
+  int32_t first_block;         // this job's workgroups in a job-table launch:
+  int32_t nblk;                //   first_block .. first_block + nblk - 1
 };
 
-// A device table of jobs (blockIdx.y picks one), or one job by value.
+// A device table of jobs with the job of every workgroup (block_job), or one
+// job by value (jobs == null; the whole grid works on it).
 struct TopkJobs {
   const TopkJob *jobs;
+  const int32_t *block_job;
   TopkJob single;
 };
 
 size_t topk_workspace_bytes(int top_k);
 TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws);
-hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu_count, hipStream_t stream);
+// Workgroups per job: sets first_block and nblk of every job, returns their sum.
+int64_t topk_assign_blocks(TopkJob *jobs, int n_jobs, int cu_count);
+// Upper bound of topk_assign_blocks over every device, for workspace layouts.
+int64_t topk_max_blocks(const int64_t *n, int n_jobs);
+hipError_t launch_topk_jobs(const TopkJobs &J, int64_t total_blocks, int64_t max_n, hipStream_t stream);
 hipError_t launch_topk(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws, int cu_count,
                        hipStream_t stream);
 

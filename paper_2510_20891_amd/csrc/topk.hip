@@ -16,6 +16,8 @@
 // compaction pass, orders the winners, so a top-k is 4 to 7 launches.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 #include "score_internal.h"
 
@@ -53,12 +55,12 @@ __device__ __forceinline__ float key_value(uint32_t k) {
 constexpr int STREAM = 4;
 
 template <typename F>
-__device__ __forceinline__ void for_each_stat(const float *__restrict__ stat, int64_t n, F &&f) {
+__device__ __forceinline__ void for_each_stat(const float *__restrict__ stat, int64_t n, int lb, int nblk, F &&f) {
   const int64_t n4 = n >> 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
   typedef float f4 __attribute__((ext_vector_type(4)));
   const gmem<const f4> *s4 = global(reinterpret_cast<const f4 *>(stat));
-  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < n4; q0 += STREAM * stride) {
+  for (int64_t q0 = (int64_t)lb * blockDim.x + threadIdx.x; q0 < n4; q0 += STREAM * stride) {
     f4 v[STREAM];
 #pragma unroll
     for (int u = 0; u < STREAM; ++u) {
@@ -76,7 +78,7 @@ __device__ __forceinline__ void for_each_stat(const float *__restrict__ stat, in
       }
     }
   }
-  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) f(i, stat[i]);
+  for (int64_t i = 4 * n4 + (int64_t)lb * blockDim.x + threadIdx.x; i < n; i += stride) f(i, stat[i]);
 }
 
 // Count `bin` in the LDS histogram if `in`.  Statistics crowd into a few bins
@@ -126,16 +128,17 @@ __device__ __forceinline__ void add_window(uint32_t *lh, uint32_t base, uint64_t
   }
 }
 
-__device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, uint32_t *lh, int shift, uint32_t mask) {
+__device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, int lb, int nblk, uint32_t *lh, int shift,
+                                                 uint32_t mask) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   const gmem<const f4> *s4 = global(reinterpret_cast<const f4 *>(stat));
   const int64_t n4 = n >> 2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)nblk * blockDim.x;
   const int lane = (int)__lane_id();
   uint32_t base = 0u;
   uint64_t packed = 0ull;
   int groups = 0;
-  for (int64_t q0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 - lane < n4; q0 += STREAM * stride) {
+  for (int64_t q0 = (int64_t)lb * blockDim.x + threadIdx.x; q0 - lane < n4; q0 += STREAM * stride) {
     f4 v[STREAM];
 #pragma unroll
     for (int u = 0; u < STREAM; ++u) {
@@ -173,7 +176,7 @@ __device__ __forceinline__ void first_digit_hist(const float *stat, int64_t n, u
     }
   }
   if (groups % 15 != 0) add_window(lh, base, packed);
-  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+  for (int64_t i = 4 * n4 + (int64_t)lb * blockDim.x + threadIdx.x; i < n; i += stride)
     atomicAdd(&lh[(order_key(stat[i]) >> shift) & mask], 1u);
 }
 
@@ -211,13 +214,13 @@ __device__ __forceinline__ void flush_hist(const uint32_t *lh, uint32_t *gh, int
 __device__ __forceinline__ uint32_t read_bin(const uint32_t *bin);
 __device__ __forceinline__ void clear_bin(uint32_t *bin);
 
-__device__ __forceinline__ bool finish_pass(TopkState *st, int nb) {
+__device__ __forceinline__ bool finish_pass(TopkState *st, int nb, int lb, int nblk) {
   __shared__ uint32_t flag;
-  const uint32_t G = TOPK_GROUPS, g = blockIdx.x % G;
+  const uint32_t G = TOPK_GROUPS, g = (uint32_t)lb % G, nw = (uint32_t)nblk;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t members = (gridDim.x - g + G - 1) / G;     // workgroups b < gridDim.x with b mod G == g
+    const uint32_t members = (nw - g + G - 1) / G;     // workgroups b < nblk with b mod G == g
     flag = atomicAdd(&st->arrive[g * TOPK_ARRIVE_STRIDE], 1u) == members - 1u ? 1u : 0u;
   }
   __syncthreads();
@@ -241,7 +244,7 @@ __device__ __forceinline__ bool finish_pass(TopkState *st, int nb) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    const uint32_t groups = gridDim.x < G ? gridDim.x : G;
+    const uint32_t groups = nw < G ? nw : G;
     flag = atomicAdd(&st->done, 1u) == groups - 1u ? 1u : 0u;
   }
   __syncthreads();
@@ -264,11 +267,19 @@ __device__ __forceinline__ unsigned long long get_candidate(const unsigned long 
   return __hip_atomic_load(global(c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The job of this workgroup: blockIdx.y indexes the job table, or the single
-// job passed by value when there is no table.
-__device__ __forceinline__ TopkJob job_of(const TopkJobs &J) {
-  if (J.jobs == nullptr) return J.single;
-  return load_uniform(J.jobs + blockIdx.y);
+// The job of this workgroup, its index among the job's workgroups and their
+// count: from the job table through block_job, or the single job passed by
+// value (then the whole grid works on it).
+struct JobShare {
+  TopkJob job;
+  int lb, nblk;
+};
+
+__device__ __forceinline__ JobShare job_of(const TopkJobs &J) {
+  if (J.jobs == nullptr) return JobShare{J.single, (int)blockIdx.x, (int)gridDim.x};
+  const int32_t j = load_uniform(J.block_job + blockIdx.x);
+  const TopkJob job = load_uniform(J.jobs + j);
+  return JobShare{job, (int)blockIdx.x - job.first_block, job.nblk};
 }
 
 // Run by the whole last workgroup of a pass: move the merged histogram into
@@ -340,7 +351,8 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
 // prefix found so far.
 __global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J, int shift, int width, int first,
                                                                      int last) {
-  const TopkJob job = job_of(J);
+  const JobShare js = job_of(J);
+  const TopkJob &job = js.job;
   if (job.kk == 0) return;
   __shared__ uint32_t lh[TOPK_HIST];
   const int nb = 1 << width;
@@ -349,21 +361,22 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J,
   const uint32_t prefix = first ? 0u : job.st->key_prefix;
   const uint32_t mask = (uint32_t)nb - 1u;
   if (first) {
-    first_digit_hist(job.stat, job.n, lh, shift, mask);
+    first_digit_hist(job.stat, job.n, js.lb, js.nblk, lh, shift, mask);
   } else {
-    for_each_stat(job.stat, job.n, [&](int64_t, float v) {
+    for_each_stat(job.stat, job.n, js.lb, js.nblk, [&](int64_t, float v) {
       const uint32_t k = order_key(v);
       hist_add<false>(lh, (k >> shift) & mask, (k >> hi) == (prefix >> hi));
     });
   }
-  flush_hist(lh, job.st->ghist[blockIdx.x % TOPK_GROUPS], nb);
-  if (finish_pass(job.st, nb)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
+  flush_hist(lh, job.st->ghist[js.lb % TOPK_GROUPS], nb);
+  if (finish_pass(job.st, nb, js.lb, js.nblk)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
 }
 
 // Index pass: among keys equal to the threshold, histogram of index digit
 // [shift, shift+width) of the indices that match the index prefix so far.
 __global__ __launch_bounds__(HIST_THREADS) void topk_index_pass_kernel(TopkJobs J, int shift, int width, int first) {
-  const TopkJob job = job_of(J);
+  const JobShare js = job_of(J);
+  const TopkJob &job = js.job;
   if (job.kk == 0 || job.st->tie_mode == 0u) return;
   __shared__ uint32_t lh[TOPK_HIST];
   const int nb = 1 << width;
@@ -372,12 +385,12 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_index_pass_kernel(TopkJobs 
   const uint32_t key = job.st->key_prefix;
   const uint32_t prefix = first ? 0u : job.st->idx_prefix;
   const uint32_t mask = (uint32_t)nb - 1u;
-  for_each_stat(job.stat, job.n, [&](int64_t i, float v) {
+  for_each_stat(job.stat, job.n, js.lb, js.nblk, [&](int64_t i, float v) {
     const uint32_t u = (uint32_t)i;
     hist_add<true>(lh, (u >> shift) & mask, order_key(v) == key && (hi >= 32 || (u >> hi) == (prefix >> hi)));
   });
-  flush_hist(lh, job.st->ghist[blockIdx.x % TOPK_GROUPS], nb);
-  if (finish_pass(job.st, nb)) select_digit<false>(job, lh, shift, width, first != 0, false);
+  flush_hist(lh, job.st->ghist[js.lb % TOPK_GROUPS], nb);
+  if (finish_pass(job.st, nb, js.lb, js.nblk)) select_digit<false>(job, lh, shift, width, first != 0, false);
 }
 
 // Outputs from sorted candidates (or none): positions past kk get -inf / -1.
@@ -400,10 +413,11 @@ __device__ __forceinline__ void write_results(const TopkJob &job, const unsigned
 // candidate list; the last workgroup sorts the kk candidates (descending key,
 // then ascending index, both encoded in one 64-bit word) and writes the outputs.
 __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) {
-  const TopkJob job = job_of(J);
+  const JobShare js = job_of(J);
+  const TopkJob &job = js.job;
   __shared__ unsigned long long s[EMRI_MAX_TOPK];
   if (job.kk == 0) {
-    if (blockIdx.x == 0) write_results(job, s);
+    if (js.lb == 0) write_results(job, s);
     return;
   }
   TopkState *st = job.st;
@@ -412,7 +426,7 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
   const uint32_t thr = st->idx_prefix;
   const uint32_t kk = job.kk;
   unsigned long long *cand = job.cand;
-  for_each_stat(job.stat, job.n, [&](int64_t i, float v) {
+  for_each_stat(job.stat, job.n, js.lb, js.nblk, [&](int64_t i, float v) {
     const uint32_t k = order_key(v);
     const bool sel = k > key || (k == key && (!tie || (uint32_t)i <= thr));
     if (sel) {
@@ -420,7 +434,7 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
       if (pos < kk) put_candidate(cand + pos, ((unsigned long long)k << 32) | (0xffffffffu - (uint32_t)i));
     }
   });
-  if (!finish_pass(st, 0)) return;
+  if (!finish_pass(st, 0, js.lb, js.nblk)) return;
   if (threadIdx.x == 0) clear_bin(&st->done);
   const int nc = (int)kk;
   {
@@ -512,14 +526,50 @@ TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int6
   job.cand = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + round_up(sizeof(TopkState), 256));
   job.vals = vals;
   job.idx = idx;
+  job.first_block = 0;
+  job.nblk = 1;
   return job;
 }
 
-hipError_t launch_topk_jobs(const TopkJobs &J, int n_jobs, int64_t max_n, int cu_count, hipStream_t stream) {
-  if (n_jobs <= 0) return hipSuccess;
-  const int64_t work = (max_n + 4 * HIST_THREADS - 1) / (4 * HIST_THREADS);
-  const int gx = (int)(work < (int64_t)cu_count * 4 ? (work > 0 ? work : 1) : (int64_t)cu_count * 4);
-  const dim3 grid(gx, n_jobs), block(HIST_THREADS);
+namespace {
+constexpr int64_t kMinShare = 4 * STREAM * HIST_THREADS;   // one group of loads per thread
+constexpr int64_t kMaxBlocksPerJob = 1024;
+
+int64_t blocks_for(int64_t n, int64_t chunk, int64_t cap) {
+  return std::max<int64_t>(1, std::min(cap, (n + chunk - 1) / chunk));
+}
+}  // namespace
+
+// Every workgroup takes at least one group of loads per thread; with many or
+// long jobs the share grows so that all jobs together use about eight
+// workgroups per CU, split in proportion to their lengths (each workgroup pays
+// a fixed merge and arrival, and a job with too few workgroups streams its
+// statistic at the pace of their loads in flight).  A job takes at most four
+// per CU and at most 1024.
+int64_t topk_assign_blocks(TopkJob *jobs, int n_jobs, int cu_count) {
+  int64_t total_n = 0;
+  for (int j = 0; j < n_jobs; ++j) total_n += jobs[j].n;
+  const int64_t target = (int64_t)cu_count * 8;
+  const int64_t chunk = std::max<int64_t>(kMinShare, (total_n + target - 1) / target);
+  const int64_t cap = std::min<int64_t>(kMaxBlocksPerJob, (int64_t)cu_count * 4);
+  int64_t first = 0;
+  for (int j = 0; j < n_jobs; ++j) {
+    jobs[j].first_block = (int32_t)first;
+    jobs[j].nblk = (int32_t)blocks_for(jobs[j].n, chunk, cap);
+    first += jobs[j].nblk;
+  }
+  return first;
+}
+
+int64_t topk_max_blocks(const int64_t *n, int n_jobs) {
+  int64_t total = 0;
+  for (int j = 0; j < n_jobs; ++j) total += blocks_for(n[j], kMinShare, kMaxBlocksPerJob);
+  return total;
+}
+
+hipError_t launch_topk_jobs(const TopkJobs &J, int64_t total_blocks, int64_t max_n, hipStream_t stream) {
+  if (total_blocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total_blocks), block(HIST_THREADS);
   static const int key_shift[3] = {20, 10, 0}, key_width[3] = {12, 10, 10};
   for (int pass = 0; pass < 3; ++pass)
     hipLaunchKernelGGL(topk_key_pass_kernel, grid, block, 0, stream, J, key_shift[pass], key_width[pass],
@@ -540,8 +590,10 @@ hipError_t launch_topk(const float *stat, int64_t n, int top_k, float *vals, int
   if (top_k <= 0) return hipSuccess;
   TopkJobs J;
   J.jobs = nullptr;
+  J.block_job = nullptr;
   J.single = make_topk_job(stat, n, top_k, vals, idx, ws);
-  return launch_topk_jobs(J, 1, n, cu_count, stream);
+  const int64_t blocks = topk_assign_blocks(&J.single, 1, cu_count);
+  return launch_topk_jobs(J, blocks, n, stream);
 }
 
 }  // namespace emri
