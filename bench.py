@@ -82,7 +82,7 @@ def cpu_baseline(P, f0, U, C, t_sft, n_sample: int) -> dict:
     evals = n_sample * P.shape[0]
     return {"value": evals / wall, "unit": "template-segment evals/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n_sample} of the 1e7 templates x {P.shape[0]} segments, FP64 NumPy oracle, "
-                      f"{cores} worker processes, {wall:.2f} s wall"}
+                      f"{cores} worker processes, {wall:.2f} s wall ({wall * cores:.0f} core-seconds)"}
 
 
 def measured_traffic():
@@ -321,7 +321,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--templates", type=int, default=10_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 21)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="precision,batched,serving",
                     help="comma-separated forms measured after the headline (precision, batched, serving, or none)")

@@ -11,6 +11,7 @@
 
 #include "common.h"
 #include "score_internal.h"
+#include "topk_internal.h"
 
 using namespace emri;
 

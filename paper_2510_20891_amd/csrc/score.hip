@@ -34,6 +34,7 @@
 
 #include "common.h"
 #include "score_internal.h"
+#include "topk_internal.h"
 #include "staging.h"
 
 namespace emri {

@@ -20,6 +20,7 @@
 
 #include "common.h"
 #include "score_internal.h"
+#include "topk_internal.h"
 
 namespace emri {
 namespace {
