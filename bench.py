@@ -332,8 +332,8 @@ def main() -> int:
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(templates would shard across GPUs with one top-k exchange; see the design notes)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(templates would shard across GPUs, each keeping its local top-k, merged by one exchange)",
               file=sys.stderr)
         return 2
 

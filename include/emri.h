@@ -37,7 +37,7 @@ typedef enum {
   EMRI_ERANGE = -2,       /* a size product overflows                             */
   EMRI_ENOMEM = -3,       /* the workspace passed is smaller than required        */
   EMRI_EDEVICE = -4,      /* a HIP call or kernel launch failed                   */
-  EMRI_EUNSUPPORTED = -5  /* a valid request this build does not implement        */
+  EMRI_EUNSUPPORTED = -5  /* a valid request the library does not implement      */
 } emri_status;
 
 typedef enum { EMRI_F32 = 0, EMRI_F16 = 1 } emri_pdtype;   /* power storage type */

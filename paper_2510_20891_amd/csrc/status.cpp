@@ -47,7 +47,7 @@ extern "C" const char *emri_status_string(int status) {
     case EMRI_ERANGE: return "EMRI_ERANGE: size overflow";
     case EMRI_ENOMEM: return "EMRI_ENOMEM: workspace too small";
     case EMRI_EDEVICE: return "EMRI_EDEVICE: HIP error";
-    case EMRI_EUNSUPPORTED: return "EMRI_EUNSUPPORTED: not supported by this build";
+    case EMRI_EUNSUPPORTED: return "EMRI_EUNSUPPORTED: not supported by this library";
     default: return "unknown emri status";
   }
 }
