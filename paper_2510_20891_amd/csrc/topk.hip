@@ -287,10 +287,13 @@ __device__ __forceinline__ JobShare job_of(const TopkJobs &J) {
 // LDS (leaving the state's zero for the next pass), then one wave scans it from
 // the largest digit down (keys) or the smallest up (indices) and fixes the
 // digit that holds the need-th element.  `first`: the first pass of its kind
-// (its prefix starts empty; the first key pass needs kk elements); `last`: the
-// final key pass, which also sets up the tie passes and the compaction.
+// (its prefix starts empty; the first key pass needs kk elements); `decide`:
+// the second key pass, which chooses between gathering and the remaining
+// radix passes; `last`: the final key pass, which also sets up the tie passes
+// and the compaction.
 template <bool KEYS>
-__device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int width, bool first, bool last) {
+__device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int width, bool first, bool decide,
+                             bool last) {
   TopkState *st = job.st;
   const int nb = 1 << width;
   // The whole table, without branches, so that the loads are in flight
@@ -332,6 +335,18 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
       if (KEYS) {
         st->key_prefix = (first ? 0u : st->key_prefix) | ((uint32_t)d << shift);
         st->need = left;
+        if (decide) {
+          // h keys share the new prefix: if they and the winners fit in LDS,
+          // the next pass gathers them and orders the winners (no further
+          // digit, index or compaction pass has work)
+          const uint32_t gather = h + job.kk <= (uint32_t)TOPK_GATHER ? 1u : 0u;
+          st->gathered = gather;
+          if (gather) {
+            st->tie_mode = 0u;
+            st->count = 0u;
+            st->bcount = 0u;
+          }
+        }
         if (last) {
           st->eq_count = h;
           st->tie_mode = h > left ? 1u : 0u;
@@ -348,20 +363,178 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
   }
 }
 
-// Key pass: histogram of digit [shift, shift+width) of the keys that match the
-// prefix found so far.
-__global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J, int shift, int width, int first,
-                                                                     int last) {
+// Outputs from sorted candidates (or none): positions past kk get -inf / -1.
+__device__ __forceinline__ void write_results(const TopkJob &job, const unsigned long long *s) {
+  const int kk = (int)job.kk;
+  for (int i = threadIdx.x; i < job.top_k; i += blockDim.x) {
+    if (i < kk) {
+      const unsigned long long c = s[i];
+      job.vals[i] = key_value((uint32_t)(c >> 32));
+      job.idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
+    } else {
+      job.vals[i] = -__builtin_inff();
+      job.idx[i] = -1;
+    }
+  }
+}
+
+// A word's place among nc distinct words is the number of larger words; each
+// thread ranks M of them against all.
+template <int M>
+__device__ void rank_and_write(const TopkJob &job, unsigned long long *s, int nc, int cap) {
+  unsigned long long w[M];
+  int rank[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    w[m] = i < nc ? s[i] : ~0ull;
+    rank[m] = 0;
+  }
+  // zero words (below every candidate) pad the list to a multiple of 8
+  if (threadIdx.x < 8 && nc + (int)threadIdx.x < cap) s[nc + threadIdx.x] = 0ull;
+  __syncthreads();
+  const int n8 = ((nc + 7) & ~7) < cap ? ((nc + 7) & ~7) : cap;
+#pragma unroll 8
+  for (int j = 0; j < n8; ++j) {
+    const unsigned long long o = s[j];
+#pragma unroll
+    for (int m = 0; m < M; ++m) rank[m] += o > w[m] ? 1 : 0;
+  }
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    if (i < nc) {
+      job.vals[rank[m]] = key_value((uint32_t)(w[m] >> 32));
+      job.idx[rank[m]] = (int64_t)(0xffffffffu - (uint32_t)(w[m] & 0xffffffffull));
+    }
+  }
+  for (int i = nc + threadIdx.x; i < job.top_k; i += blockDim.x) {
+    job.vals[i] = -__builtin_inff();
+    job.idx[i] = -1;
+  }
+}
+
+// Orders the nc distinct (key, index) words in s[0..nc) (LDS, room for cap
+// words) in decreasing order and writes the outputs; the whole workgroup
+// calls it.  Up to RANK_SORT_MAX words by rank counting, above by a bitonic
+// network over the next power of two.
+__device__ void order_and_write(const TopkJob &job, unsigned long long *s, int nc, int cap) {
+  if (nc <= HIST_THREADS) return rank_and_write<1>(job, s, nc, cap);
+  if (nc <= 2 * HIST_THREADS) return rank_and_write<2>(job, s, nc, cap);
+  if (nc <= RANK_SORT_MAX) return rank_and_write<RANK_SORT_MAX / HIST_THREADS>(job, s, nc, cap);
+  int p2 = 1;
+  while (p2 < nc) p2 <<= 1;
+  for (int i = nc + threadIdx.x; i < p2; i += blockDim.x) s[i] = 0ull;
+  __syncthreads();
+  for (int size = 2; size <= p2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < p2; i += blockDim.x) {
+        const int partner = i ^ stride;
+        if (partner > i) {
+          const bool desc = (i & size) == 0;
+          const unsigned long long a = s[i], b = s[partner];
+          if (desc ? (a < b) : (a > b)) {
+            s[i] = b;
+            s[partner] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  write_results(job, s);
+}
+
+// Gathering form of the last key pass, taken when the second pass found that
+// the keys sharing the k-th key's 22 leading bits (the boundary) and the kk
+// winners fit in LDS together.  Keys above the boundary are winners, exactly
+// kk - need of them; the boundary words are gathered too, and the last
+// workgroup keeps the `need` largest of them by rank (keys, then smaller
+// indices, decide: the words are distinct), then orders all kk winners.  This
+// replaces the third digit pass, the index passes and the compaction pass.
+__device__ void gather_winners(const JobShare &js, unsigned long long *s) {
+  const TopkJob &job = js.job;
+  TopkState *st = job.st;
+  const uint32_t P = st->key_prefix >> 10;
+  const uint32_t need = st->need, above = job.kk - need;
+  for_each_stat(job.stat, job.n, js.lb, js.nblk, [&](int64_t i, float v) {
+    const uint32_t k = order_key(v);
+    const uint32_t hk = k >> 10;
+    if (hk >= P) {
+      const unsigned long long w = ((unsigned long long)k << 32) | (0xffffffffu - (uint32_t)i);
+      if (hk > P) {
+        const uint32_t pos = atomicAdd(&st->count, 1u);
+        if (pos < above) put_candidate(job.cand + pos, w);
+      } else {
+        const uint32_t pos = atomicAdd(&st->bcount, 1u);
+        if (pos < (uint32_t)TOPK_GATHER) put_candidate(job.bnd + pos, w);
+      }
+    }
+  });
+  if (!finish_pass(st, 0, js.lb, js.nblk)) return;
+  if (threadIdx.x == 0) clear_bin(&st->done);
+  const uint32_t nbw = read_bin(&st->bcount);
+  const int nb = (int)(nbw < (uint32_t)TOPK_GATHER ? nbw : (uint32_t)TOPK_GATHER);
+  constexpr int PER = TOPK_GATHER / HIST_THREADS;
+  // boundary words into LDS (loads first, clamped in bounds, no branches)
+  unsigned long long w[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    w[m] = get_candidate(job.bnd + (i < nb ? i : (nb > 0 ? nb - 1 : 0)));
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    if (i < nb) s[i] = w[m];
+    else w[m] = 0ull;
+  }
+  __syncthreads();
+  int rank[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) rank[m] = 0;
+  for (int j = 0; j < nb; ++j) {
+    const unsigned long long o = s[j];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) rank[m] += o > w[m] ? 1 : 0;
+  }
+  __syncthreads();
+  // winners: those above the boundary from the candidate list, then the
+  // `need` largest boundary words at their ranks
+  unsigned long long c[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    c[m] = get_candidate(job.cand + (i < (int)above ? i : (above > 0 ? (int)above - 1 : 0)));
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int i = threadIdx.x + m * HIST_THREADS;
+    if (i < (int)above) s[i] = c[m];
+    if (i < nb && rank[m] < (int)need) s[above + rank[m]] = w[m];
+  }
+  __syncthreads();
+  order_and_write(job, s, (int)job.kk, TOPK_GATHER);
+}
+
+// Key pass `pass` (0, 1, 2): histogram of digit [shift, shift+width) of the
+// keys that match the prefix found so far.  The last pass instead gathers
+// and orders the winners when the second pass found that they fit.
+__global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J, int shift, int width, int pass) {
   const JobShare js = job_of(J);
   const TopkJob &job = js.job;
   if (job.kk == 0) return;
   __shared__ uint32_t lh[TOPK_HIST];
+  if (pass == 2 && job.st->gathered != 0u) {
+    gather_winners(js, reinterpret_cast<unsigned long long *>(lh));
+    return;
+  }
   const int nb = 1 << width;
   clear_hist(lh, nb);
   const int hi = shift + width;
-  const uint32_t prefix = first ? 0u : job.st->key_prefix;
+  const uint32_t prefix = pass == 0 ? 0u : job.st->key_prefix;
   const uint32_t mask = (uint32_t)nb - 1u;
-  if (first) {
+  if (pass == 0) {
     first_digit_hist(job.stat, job.n, js.lb, js.nblk, lh, shift, mask);
   } else {
     for_each_stat(job.stat, job.n, js.lb, js.nblk, [&](int64_t, float v) {
@@ -370,7 +543,8 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_key_pass_kernel(TopkJobs J,
     });
   }
   flush_hist(lh, job.st->ghist[js.lb % TOPK_GROUPS], nb);
-  if (finish_pass(job.st, nb, js.lb, js.nblk)) select_digit<true>(job, lh, shift, width, first != 0, last != 0);
+  if (finish_pass(job.st, nb, js.lb, js.nblk))
+    select_digit<true>(job, lh, shift, width, pass == 0, pass == 1, pass == 2);
 }
 
 // Index pass: among keys equal to the threshold, histogram of index digit
@@ -391,22 +565,7 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_index_pass_kernel(TopkJobs 
     hist_add<true>(lh, (u >> shift) & mask, order_key(v) == key && (hi >= 32 || (u >> hi) == (prefix >> hi)));
   });
   flush_hist(lh, job.st->ghist[js.lb % TOPK_GROUPS], nb);
-  if (finish_pass(job.st, nb, js.lb, js.nblk)) select_digit<false>(job, lh, shift, width, first != 0, false);
-}
-
-// Outputs from sorted candidates (or none): positions past kk get -inf / -1.
-__device__ __forceinline__ void write_results(const TopkJob &job, const unsigned long long *s) {
-  const int kk = (int)job.kk;
-  for (int i = threadIdx.x; i < job.top_k; i += blockDim.x) {
-    if (i < kk) {
-      const unsigned long long c = s[i];
-      job.vals[i] = key_value((uint32_t)(c >> 32));
-      job.idx[i] = (int64_t)(0xffffffffu - (uint32_t)(c & 0xffffffffull));
-    } else {
-      job.vals[i] = -__builtin_inff();
-      job.idx[i] = -1;
-    }
-  }
+  if (finish_pass(job.st, nb, js.lb, js.nblk)) select_digit<false>(job, lh, shift, width, first != 0, false, false);
 }
 
 // Compaction: every element above the threshold, and those equal to it that
@@ -422,6 +581,7 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
     return;
   }
   TopkState *st = job.st;
+  if (st->gathered != 0u) return;                 // the last key pass has done it
   const uint32_t key = st->key_prefix;
   const bool tie = st->tie_mode != 0u;
   const uint32_t thr = st->idx_prefix;
@@ -453,68 +613,14 @@ __global__ __launch_bounds__(HIST_THREADS) void topk_compact_kernel(TopkJobs J) 
     }
   }
   __syncthreads();
-  if (nc <= RANK_SORT_MAX) {
-    // the words are distinct: a word's place is the number of larger words
-    constexpr int M = RANK_SORT_MAX / HIST_THREADS;
-    unsigned long long w[M];
-    int rank[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int i = threadIdx.x + m * HIST_THREADS;
-      w[m] = i < nc ? s[i] : ~0ull;
-      rank[m] = 0;
-    }
-    // zero words (below every candidate) pad the list to a multiple of 8
-    if (threadIdx.x < 8 && nc + threadIdx.x < EMRI_MAX_TOPK) s[nc + threadIdx.x] = 0ull;
-    __syncthreads();
-#pragma unroll 8
-    for (int j = 0; j < ((nc + 7) & ~7); ++j) {
-      const unsigned long long o = s[j];
-#pragma unroll
-      for (int m = 0; m < M; ++m) rank[m] += o > w[m] ? 1 : 0;
-    }
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-      const int i = threadIdx.x + m * HIST_THREADS;
-      if (i < nc) {
-        job.vals[rank[m]] = key_value((uint32_t)(w[m] >> 32));
-        job.idx[rank[m]] = (int64_t)(0xffffffffu - (uint32_t)(w[m] & 0xffffffffull));
-      }
-    }
-    for (int i = nc + threadIdx.x; i < job.top_k; i += blockDim.x) {
-      job.vals[i] = -__builtin_inff();
-      job.idx[i] = -1;
-    }
-    return;
-  }
-  // bitonic network, descending, over the next power of two
-  int p2 = 1;
-  while (p2 < nc) p2 <<= 1;
-  for (int i = nc + threadIdx.x; i < p2; i += blockDim.x) s[i] = 0ull;
-  __syncthreads();
-  for (int size = 2; size <= p2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < p2; i += blockDim.x) {
-        const int partner = i ^ stride;
-        if (partner > i) {
-          const bool desc = (i & size) == 0;
-          const unsigned long long a = s[i], b = s[partner];
-          if (desc ? (a < b) : (a > b)) {
-            s[i] = b;
-            s[partner] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  write_results(job, s);
+  order_and_write(job, s, nc, EMRI_MAX_TOPK);
 }
 
 }  // namespace
 
 size_t topk_workspace_bytes(int top_k) {
-  return round_up(sizeof(TopkState), 256) + round_up((size_t)(top_k > 0 ? top_k : 1) * 8, 256);
+  return round_up(sizeof(TopkState), 256) + round_up((size_t)(top_k > 0 ? top_k : 1) * 8, 256) +
+         (size_t)TOPK_GATHER * 8;
 }
 
 TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws) {
@@ -525,6 +631,8 @@ TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int6
   job.kk = (uint32_t)(n < (int64_t)top_k ? n : (int64_t)top_k);
   job.st = reinterpret_cast<TopkState *>(ws);
   job.cand = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + round_up(sizeof(TopkState), 256));
+  job.bnd = reinterpret_cast<unsigned long long *>(reinterpret_cast<char *>(ws) + round_up(sizeof(TopkState), 256) +
+                                                   round_up((size_t)(top_k > 0 ? top_k : 1) * 8, 256));
   job.vals = vals;
   job.idx = idx;
   job.first_block = 0;
@@ -573,8 +681,7 @@ hipError_t launch_topk_jobs(const TopkJobs &J, int64_t total_blocks, int64_t max
   const dim3 grid((unsigned)total_blocks), block(HIST_THREADS);
   static const int key_shift[3] = {20, 10, 0}, key_width[3] = {12, 10, 10};
   for (int pass = 0; pass < 3; ++pass)
-    hipLaunchKernelGGL(topk_key_pass_kernel, grid, block, 0, stream, J, key_shift[pass], key_width[pass],
-                       pass == 0 ? 1 : 0, pass == 2 ? 1 : 0);
+    hipLaunchKernelGGL(topk_key_pass_kernel, grid, block, 0, stream, J, key_shift[pass], key_width[pass], pass);
   // index digits cover the bits of the largest index, top digit first
   int bits = 1;
   while (bits < 31 && ((int64_t)1 << bits) < max_n) ++bits;

@@ -12,6 +12,7 @@
 namespace emri {
 
 constexpr int TOPK_HIST = 4096;        // bins of one radix pass (digits of at most 12 bits)
+constexpr int TOPK_GATHER = 2048;      // (key, index) words the last key pass may order in LDS
 
 // Top-k state of one job.  The histograms and counters must be zero before
 // the first pass: topk_state_reset, run by the prep kernels ahead of the
@@ -29,7 +30,9 @@ struct TopkState {
   uint32_t count;             // compaction cursor
   uint32_t eq_count;          // number of keys equal to the threshold
   uint32_t done;              // groups of the current pass that have finished
-  uint32_t pad[24];
+  uint32_t gathered;          // 1: the last key pass gathers and orders the winners itself
+  uint32_t bcount;            // gathering cursor of the boundary words
+  uint32_t pad[22];
   uint32_t arrive[TOPK_GROUPS * TOPK_ARRIVE_STRIDE];   // finished workgroups of each group
   uint32_t hist[TOPK_HIST];                          // histogram of the pass, all groups
   uint32_t ghist[TOPK_GROUPS][TOPK_HIST];            // histogram of the pass, one group
@@ -52,6 +55,7 @@ struct TopkJob {
   uint32_t kk;                 // min(n, top_k)
   TopkState *st;
   unsigned long long *cand;    // kk candidate (key, index) pairs
+  unsigned long long *bnd;     // TOPK_GATHER words: keys sharing the k-th key's 22 leading bits
   float *vals;
   int64_t *idx;
   int32_t first_block;         // this job's workgroups in a job-table launch:
