@@ -398,6 +398,14 @@ constexpr int tpl_alt(int K) {
   return t < 1 ? 1 : t;
 }
 constexpr bool has_alt(int K) { return K == 8 || K == 16; }
+// The standalone kernel at K = 8 with FP32 power fits a tenth slot in its 256
+// VGPRs without spilling: fewer tiles, so each row is staged fewer times
+// (measured ~2 % faster).  With FP16 power it does not pay, and the batched
+// kernel, which holds more state, would spill.
+template <int K, typename PT>
+constexpr int tpl_fast() {
+  return (K == 8 && sizeof(PT) == 4) ? 10 : tpl_for(K);
+}
 
 template <typename Kern>
 hipError_t set_lds(Kern kern, size_t lds) {
@@ -407,7 +415,7 @@ hipError_t set_lds(Kern kern, size_t lds) {
 
 template <int K, typename PT>
 hipError_t launch_fast_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
-  constexpr int TPL = tpl_for(K);
+  constexpr int TPL = tpl_fast<K, PT>();
   auto kern = score_fast_kernel<K, TPL, PT>;
   hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
