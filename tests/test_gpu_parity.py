@@ -341,6 +341,27 @@ def test_topk_of_wide_and_narrow_statistics(gpu_lib, sigma, k):
     assert np.array_equal(gpu["topk_val"], ov.astype(np.float32))
 
 
+@pytest.mark.parametrize("n_close,k", [(1500, 256), (1900, 256), (300, 1000), (5, 2000)])
+def test_topk_boundary_sizes(gpu_lib, n_close, k):
+    """n_close templates land on bins whose power differs only in the lowest
+    mantissa bits (their keys share the 22 leading bits, with repeats), the
+    rest on bins of power 0.5.  Depending on n_close + k the last key pass
+    either gathers the boundary keys (up to 2048 words) or falls back to the
+    radix passes; both must give exactly the first k by (-S, index)."""
+    n, n_bins, t = 200_000, 2048, 1.0
+    P = np.full((1, n_bins), 0.5)
+    P[0, :1024] = 1.0 + np.arange(1024) * 2.0 ** -23
+    g = np.random.default_rng(n_close + k)
+    c = g.integers(1024, 2048, n)
+    close = g.choice(n, n_close, replace=False)
+    c[close] = g.integers(0, 1024, n_close)
+    gpu = score_gpu(gpu_lib, P, np.zeros(1), np.ones((1, 1)), c.astype(np.float32)[:, None], t, k)
+    assert np.array_equal(gpu["stat"], P[0, c].astype(np.float32))
+    ov, oi = oracle.topk_order(P[0, c], k)
+    assert np.array_equal(gpu["topk_idx"], oi)
+    assert np.array_equal(gpu["topk_val"], ov.astype(np.float32))
+
+
 def test_topk_nan_and_negative(gpu_lib):
     n_seg, n_bins, t = 2, 8, 1.0
     P = np.array([[1, -3, np.nan, 0, 2, 5, -0.0, 4], [0, 0, 0, 0, 0, 0, 0, 0]], dtype=np.float64)
