@@ -190,13 +190,18 @@ __device__ __forceinline__ void clear_hist(uint32_t *lh, int nb) {
 // so neighbouring bins, which the leading digit fills at once, sit on
 // different cache lines and their atomics are not serialised together.
 constexpr int GH_ROWS = 8, GH_COLS = TOPK_HIST / GH_ROWS;
+// Agent-scope add to a device-memory bin (a global, not flat, atomic).
+__device__ __forceinline__ void add_bin(uint32_t *bin, uint32_t v) {
+  __hip_atomic_fetch_add(global(bin), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ int gh_word(int b) { return (b % GH_ROWS) * GH_COLS + b / GH_ROWS; }
 __device__ __forceinline__ int gh_bin(int w) { return (w % GH_COLS) * GH_ROWS + w / GH_COLS; }
 
 __device__ __forceinline__ void flush_hist(const uint32_t *lh, uint32_t *gh, int nb) {
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += blockDim.x)
-    if (lh[b]) atomicAdd(&gh[gh_word(b)], lh[b]);
+    if (lh[b]) add_bin(&gh[gh_word(b)], lh[b]);
 }
 
 // Everything one workgroup leaves for another goes through agent-scope
@@ -206,7 +211,7 @@ __device__ __forceinline__ void flush_hist(const uint32_t *lh, uint32_t *gh, int
 // that no address takes more than about 128 atomics (atomics on one address
 // are serialised, and the workgroups of a pass finish at about the same time):
 // a workgroup adds its LDS histogram into its group's histogram, waits until
-// its atomics have completed (vmcnt) and counts itself on the group's arrival
+// its atomics have completed (s_waitcnt) and counts itself on the group's arrival
 // counter; the last of a group moves the group histogram into the pass
 // histogram, waits, and counts the group on `done`; the workgroup that
 // completes `done` sees every other workgroup's completed atomics.  No
@@ -218,7 +223,7 @@ __device__ __forceinline__ void clear_bin(uint32_t *bin);
 __device__ __forceinline__ bool finish_pass(TopkState *st, int nb, int lb, int nblk) {
   __shared__ uint32_t flag;
   const uint32_t G = TOPK_GROUPS, g = (uint32_t)lb % G, nw = (uint32_t)nblk;
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t members = (nw - g + G - 1) / G;     // workgroups b < nblk with b mod G == g
@@ -236,13 +241,13 @@ __device__ __forceinline__ bool finish_pass(TopkState *st, int nb, int lb, int n
     for (int m = 0; m < PER; ++m) {
       const int w = threadIdx.x + m * HIST_THREADS;
       if (h[m]) {
-        atomicAdd(&st->hist[gh_bin(w)], h[m]);
+        add_bin(&st->hist[gh_bin(w)], h[m]);
         clear_bin(&st->ghist[g][w]);
       }
     }
   }
   if (threadIdx.x == 0) clear_bin(&st->arrive[g * TOPK_ARRIVE_STRIDE]);
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     const uint32_t groups = nw < G ? nw : G;
