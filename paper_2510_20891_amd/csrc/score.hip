@@ -316,17 +316,34 @@ __device__ __forceinline__ void prep_one(const PrepJob &job, bool reset_topk) {
     job.seg[(size_t)a * stride] = f0[a] * t_sft;
     for (int k = 0; k < K; ++k) job.seg[(size_t)a * stride + 1 + k] = U[(size_t)a * K + k] * t_sft;
   }
-  for (int col = 0; col <= K; ++col) {
-    double m = 0.0;
+  // column maxima eight columns at a time, so that the eight shuffle chains
+  // of a group run interleaved
+  for (int c0 = 0; c0 <= K; c0 += 8) {
+    double m[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) m[j] = 0.0;
     for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
-      const double b = abs_bound(col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft);
-      m = b > m ? b : m;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int col = c0 + j;
+        if (col <= K) {
+          const double b = abs_bound(col == 0 ? f0[a] * t_sft : U[(size_t)a * K + col - 1] * t_sft);
+          m[j] = b > m[j] ? b : m[j];
+        }
+      }
     }
     for (int off = 32; off > 0; off >>= 1) {
-      const double o = __shfl_xor(m, off, 64);
-      m = o > m ? o : m;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const double o = __shfl_xor(m[j], off, 64);
+        m[j] = o > m[j] ? o : m[j];
+      }
     }
-    if (lane == 0) red[wave][col] = m;
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (c0 + j <= K) red[wave][c0 + j] = m[j];
+    }
   }
   __syncthreads();
   if (threadIdx.x <= K) {

@@ -289,9 +289,9 @@ __device__ __forceinline__ JobShare job_of(const TopkJobs &J) {
 }
 
 // Run by the whole last workgroup of a pass: move the merged histogram into
-// LDS (leaving the state's zero for the next pass), then one wave scans it from
-// the largest digit down (keys) or the smallest up (indices) and fixes the
-// digit that holds the need-th element.  `first`: the first pass of its kind
+// LDS (leaving the state's zero for the next pass), then the workgroup scans it
+// from the largest digit down (keys) or the smallest up (indices) and fixes
+// the digit that holds the need-th element.  `first`: the first pass of its kind
 // (its prefix starts empty; the first key pass needs kk elements); `decide`:
 // the second key pass, which chooses between gathering and the remaining
 // radix passes; `last`: the final key pass, which also sets up the tie passes
@@ -313,13 +313,15 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
   for (int m = 0; m < PER; ++m) clear_bin(&st->hist[threadIdx.x + m * HIST_THREADS]);
   if (threadIdx.x == 0) clear_bin(&st->done);
   __syncthreads();
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
-  const int per = (nb + 63) >> 6;
-  // ordinal o = lane*per + i  <->  digit (KEYS ? nb-1-o : o)
+  // every thread takes `per` consecutive ordinals; a block-wide scan of their
+  // counts finds the thread whose ordinals hold the need-th element
+  __shared__ uint32_t wave_total[HIST_THREADS / 64];
+  const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+  const int per = (nb + HIST_THREADS - 1) / HIST_THREADS;
+  // ordinal o = threadIdx.x*per + i  <->  digit (KEYS ? nb-1-o : o)
   uint32_t mine = 0;
   for (int i = 0; i < per; ++i) {
-    const int o = lane * per + i;
+    const int o = (int)threadIdx.x * per + i;
     if (o < nb) mine += lh[KEYS ? nb - 1 - o : o];
   }
   uint32_t incl = mine;
@@ -327,12 +329,15 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
     const uint32_t t = __shfl_up(incl, off, 64);
     if (lane >= off) incl += t;
   }
+  if (lane == 63) wave_total[wave] = incl;
+  __syncthreads();
+  for (int w = 0; w < wave; ++w) incl += wave_total[w];
   const uint32_t excl = incl - mine;
   const uint32_t need = KEYS ? (first ? job.kk : st->need) : st->idx_need;
   if (!(excl < need && need <= incl)) return;
   uint32_t before = excl;
   for (int i = 0; i < per; ++i) {
-    const int o = lane * per + i;
+    const int o = (int)threadIdx.x * per + i;
     const int d = KEYS ? nb - 1 - o : o;
     const uint32_t h = lh[d];
     if (before + h >= need) {
