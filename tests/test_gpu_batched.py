@@ -69,6 +69,37 @@ def test_batched_equals_standalone(gpu_lib, dtype):
     check_equal(emri, probs)
 
 
+@pytest.mark.parametrize("K", [1, 3, 4, 5, 12, 16])
+@pytest.mark.parametrize("precision", ["plain", "mixed"])
+def test_batched_other_K(gpu_lib, K, precision):
+    """The batched kernels of other basis sizes: every problem equals its
+    standalone call bit for bit, and sampled statistics match the oracle."""
+    import torch
+    emri = gpu_lib
+    g = np.random.default_rng(40 + K)
+    probs, raw = [], []
+    for i, (n_seg, n_bins, n, top_k) in enumerate([(17, 1200, 6000, 32), (9, 400, 777, 5), (30, 2600, 11000, 100)]):
+        t = 163840.0
+        P = g.exponential(size=(n_seg, n_bins))
+        spec = emri.spectrogram_from_power(P, t, "f16")
+        f0 = g.uniform(0.3, 0.7, n_seg) * n_bins / t
+        U = g.standard_normal((n_seg, K)) * (15.0 / t)
+        C = g.uniform(-3, 3, (n, K)).astype(np.float32)
+        probs.append(emri.Problem(spec, _t(f0), _t(U), _t(C), top_k=top_k))
+        raw.append((spec, f0, U, C))
+    emri.BatchPlan(probs, K, precision=precision).run()
+    torch.cuda.synchronize()
+    for pb, (spec, f0, U, C) in zip(probs, raw):
+        ref = emri.score_tracks(pb.spec, pb.f0, pb.U, pb.coeffs, pb.top_k, precision=precision)
+        torch.cuda.synchronize()
+        assert torch.equal(pb.stat, ref["stat"])
+        assert torch.equal(pb.topk_idx, ref["topk_idx"])
+        rows = np.arange(0, C.shape[0], 97)
+        o = oracle.score_tracks(spec.power().cpu().numpy().astype(np.float64), f0, U, C[rows], spec.t_sft, 0)
+        rel = np.abs(pb.stat.cpu().numpy()[rows] - o["stat"]) / np.abs(o["stat"])
+        assert np.quantile(rel, 0.99) <= (1e-5 if precision == "plain" else 2e-3)
+
+
 @pytest.mark.parametrize("rows,tpl", [(1, 0), (2, 0), (4, 0), (0, 6)])
 def test_batched_tile_options_do_not_change_results(gpu_lib, rows, tpl):
     import torch
