@@ -3,6 +3,8 @@
 
 #include <cmath>
 
+#include <algorithm>
+
 #include "common.h"
 #include "score_internal.h"
 #include "topk_internal.h"
@@ -185,6 +187,13 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
       p.mseg = ws + L.mseg_off;
       p.mtab_bytes = mtab_bytes;
     }
+    // a plain launch with a top-k also runs the top-k's first key pass
+    size_t lds = sg.lds;
+    if (top_k > 0 && !mixed && !validate && power->n_seg > 0) {
+      p.topk = reinterpret_cast<TopkState *>(ws + L.topk_off);
+      p.topk_kk = (uint32_t)(n_tmpl < top_k ? n_tmpl : top_k);
+      lds = std::max(lds, (size_t)TOPK_HIST * sizeof(uint32_t));
+    }
     const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;
     const int grid = (int)(units < cus ? units : cus);
     p.per_block = (n_tmpl + grid - 1) / grid;
@@ -195,12 +204,13 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
       // kernel, whose segment loop is then empty
       err = launch_score(p, K, power->dtype, true, grid, sg.lds, stream);
     } else {
-      err = launch_score(p, K, power->dtype, validate, grid, sg.lds, stream);
+      err = launch_score(p, K, power->dtype, validate, grid, lds, stream);
     }
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score launch: %s", hipGetErrorString(err));
   }
   if (top_k > 0) {
-    err = launch_topk(stat_buf, n_tmpl, top_k, topk_val, topk_idx, ws + L.topk_off, cus, stream);
+    const int first_pass = (n_tmpl > 0 && !mixed && !validate && power->n_seg > 0) ? 1 : 0;
+    err = launch_topk(stat_buf, n_tmpl, top_k, topk_val, topk_idx, ws + L.topk_off, cus, stream, first_pass);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "top-k launch: %s", hipGetErrorString(err));
   }
   return EMRI_OK;

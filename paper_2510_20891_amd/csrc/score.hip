@@ -35,6 +35,7 @@
 #include "common.h"
 #include "score_internal.h"
 #include "topk_internal.h"
+#include "topk_device.h"
 #include "staging.h"
 
 namespace emri {
@@ -210,6 +211,64 @@ __device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char 
   }
 }
 
+// The first top-k key pass over this workgroup's own statistics (standalone
+// plain launches with a top-k; the top-k launch then starts at its second
+// pass).  The staging rows are no longer needed, so the LDS holds the
+// histogram of the 12-bit leading key digit, counted as the top-k's own first
+// pass does (an 8-bin register window per wave); the workgroups merge it in
+// two levels and the last one picks the digit.
+__device__ void first_key_pass_of_range(const ScoreParams &p, unsigned char *lds, int64_t j_begin, int64_t j_end) {
+  constexpr int SHIFT = 20, WIDTH = 12;
+  constexpr uint32_t MASK = (1u << WIDTH) - 1u;
+  uint32_t *lh = reinterpret_cast<uint32_t *>(lds);
+  __syncthreads();               // every statistic of this workgroup written, every row read
+  clear_hist(lh, TOPK_HIST);
+  const int lane = (int)(threadIdx.x & 63);
+  uint32_t base = 0u;
+  uint64_t packed = 0ull;
+  int count = 0;
+  bool have_base = false;
+  // wave-uniform trip count: lanes past the end count nothing; eight loads
+  // in flight per lane (the loop is otherwise latency-bound)
+  constexpr int U = 8;
+  const int64_t step = (int64_t)blockDim.x;
+  for (int64_t j0 = j_begin + (int64_t)(threadIdx.x & ~63u); j0 < j_end; j0 += U * step) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j0 + u * step + lane;
+      v[u] = j < j_end ? p.stat[j] : 0.0f;
+    }
+    if (!have_base) {            // the wave's first lane is live here
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane((order_key(v[0]) >> SHIFT) & MASK);
+      base = b0 >= 3u ? b0 - 3u : 0u;
+      have_base = true;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool live = j0 + u * step + lane < j_end;
+      const uint32_t bin = (order_key(v[u]) >> SHIFT) & MASK;
+      const uint32_t d = bin - base;
+      packed += (live && d < 8u) ? 1ull << (8u * d) : 0ull;
+      if (live && d >= 8u) atomicAdd(&lh[bin], 1u);
+    }
+    count += U;
+    if (count > 255 - U) {       // 8-bit fields
+      add_window(lh, base, packed);
+      packed = 0ull;
+      count = 0;
+    }
+  }
+  if (count > 0) add_window(lh, base, packed);
+  flush_hist(lh, p.topk->ghist[blockIdx.x % TOPK_GROUPS], TOPK_HIST);
+  if (finish_pass<SCORE_THREADS>(p.topk, TOPK_HIST, (int)blockIdx.x, (int)gridDim.x)) {
+    TopkJob job{};
+    job.st = p.topk;
+    job.kk = p.topk_kk;
+    select_digit<true, SCORE_THREADS>(job, lh, SHIFT, WIDTH, true, false, false);
+  }
+}
+
 template <int K, int TPL, typename PT>
 __global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -217,6 +276,7 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
   score_range<K, TPL, PT>(p, lds, j_begin, j_end);
+  if (p.topk) first_key_pass_of_range(p, lds, j_begin, j_end);
 }
 
 // Batched form: one persistent launch over many streams.  Workgroups claim

@@ -14,6 +14,8 @@ constexpr int EMRI_MAX_TOPK = 4096;
 constexpr int SCORE_LDS_LEAD = 16;   // bytes ahead of each LDS half's first row
 constexpr int SCORE_WAVES = SCORE_THREADS / 64;
 
+struct TopkState;
+
 struct ScoreParams {
   const void *power;          // spectrogram rows (FP32 or FP16)
   const double *seg;          // per segment: f0*T then U[alpha, k]*T, seg_stride doubles apart
@@ -36,6 +38,11 @@ struct ScoreParams {
   const void *mseg;           // per segment: MixedSeg
   int mtab_bytes;             // bytes of mtab for round_up(n_seg, 4) segments (staged in LDS first)
   float one;                  // 1.0f: FP16 power is added as fma(P, one, acc), one instruction
+  // standalone plain launches with a top-k: the top-k state whose first key
+  // pass the scoring workgroups run over their own statistics, or null
+  TopkState *topk;
+  uint32_t topk_kk;           // min(n_tmpl, top_k)
+  uint32_t pad2;
 };
 
 // Mixed-precision form: per-segment offset f0*T = I + phi with I the even

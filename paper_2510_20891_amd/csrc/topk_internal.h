@@ -76,8 +76,10 @@ TopkJob make_topk_job(const float *stat, int64_t n, int top_k, float *vals, int6
 int64_t topk_assign_blocks(TopkJob *jobs, int n_jobs, int cu_count);
 // Upper bound of topk_assign_blocks over every device, for workspace layouts.
 int64_t topk_max_blocks(const int64_t *n, int n_jobs);
-hipError_t launch_topk_jobs(const TopkJobs &J, int64_t total_blocks, int64_t max_n, hipStream_t stream);
+hipError_t launch_topk_jobs(const TopkJobs &J, int64_t total_blocks, int64_t max_n, hipStream_t stream,
+                            int first_pass = 0);
+// first_pass = 1: the scoring launch has already run the first key pass
 hipError_t launch_topk(const float *stat, int64_t n, int top_k, float *vals, int64_t *idx, void *ws, int cu_count,
-                       hipStream_t stream);
+                       hipStream_t stream, int first_pass = 0);
 
 }  // namespace emri
