@@ -139,24 +139,40 @@ __device__ __forceinline__ void step_products(const short4_t (&ua)[3][KG], const
   products_part<KG, TPL, 3>(ua, phi, pc, d);
 }
 
-// Operands of step r0: the A rows (segment r0 + lane % 4), the fractions phi
-// of f0 T (the chains' start) and the integer offsets I.
+// Operands of the products of one staging step r0: the A rows (segment
+// r0 + lane % 4), the fractions phi of f0 T (the chains' start) and the
+// integer offsets I.
 template <int KG>
-__device__ __forceinline__ void step_operands(const unsigned char *tab, const MixedSeg *ms, int r0, short4_t (&ua)[3][KG],
-                                              float4_t &phi, double (&I)[4]) {
+struct StepOps {
+  short4_t ua[3][KG];
+  float4_t phi;
+  double I[4];
+};
+
+// Issue the loads of step r0's operands (the table rows from LDS, the
+// per-segment values with scalar loads); the caller waits for them.
+template <int KG>
+__device__ __forceinline__ void issue_operands(const unsigned char *tab, const MixedSeg *ms, int r0, StepOps<KG> &op) {
   const int lane = (int)(threadIdx.x & 63);
   const short4_t *row = reinterpret_cast<const short4_t *>(tab + (size_t)(r0 + (lane & 3)) * (3 * KG * 8));
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int g = 0; g < KG; ++g) ua[a][g] = row[a * KG + g];
+    for (int g = 0; g < KG; ++g) op.ua[a][g] = row[a * KG + g];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const MixedSeg m = load_uniform(ms + r0 + r);
-    I[r] = m.I;
-    phi[r] = m.phi;
-    asm volatile("" ::"s"(I[r]));   // keep the scalar loads here, ahead of the gathers' counted waits
+    op.I[r] = m.I;
+    op.phi[r] = m.phi;
   }
+}
+
+// Keep the scalar loads of issue_operands ahead of this point (their results
+// are needed here), so that none is outstanding in the next counted waits.
+template <int KG>
+__device__ __forceinline__ void operands_landed(const StepOps<KG> &op) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) asm volatile("" ::"s"(op.I[r]));
 }
 
 // Interleave the matrix products just issued with the vector work of the same
@@ -172,27 +188,32 @@ __device__ __forceinline__ void interleave_products() {
 
 // One staging step r0 (4 segments) with the products dc of this step, while
 // the products dn of the next step are issued a quarter per segment,
-// interleaved with the address arithmetic.  The gathers of segment r are in
-// flight while the addresses of segment r+1 are computed.  Segments past
-// n_seg (last step) gather in-bounds stale data that is not added.
+// interleaved with the address arithmetic, from the operands op loaded during
+// the previous step.  The gathers of segment r are in flight while the
+// addresses of segment r+1 are computed; the operands of the step after next
+// load while the last gathers are in flight.  Segments past n_seg (last step)
+// gather in-bounds stale data that is not added.
 template <int KG, int TPL, typename PT, bool WILD>
 __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp, const unsigned char *tab,
                                            unsigned char *lds, const Pieces<KG, TPL> &pc, int r0, int half,
                                            const float4_t (&dc)[TPL], const double (&Ic)[4], float4_t (&dn)[TPL],
-                                           double (&In)[4], float (&acc)[TPL], double (&sum)[TPL]) {
+                                           double (&In)[4], StepOps<KG> &op, float (&acc)[TPL],
+                                           double (&sum)[TPL]) {
   constexpr int E = Elem<PT>::bytes;
   constexpr int NQ = kPairs * KG / 4 * TPL;       // products per quarter (lower bound)
   static_assert(TPL < 16, "lgkmcnt holds at most 15 outstanding gathers");
   pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
   const bool more = r0 + 4 < p.n_seg;
-  short4_t ua[3][KG];
-  float4_t phi;
-  step_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), more ? r0 + 4 : r0, ua, phi, In);
-  __builtin_amdgcn_s_waitcnt(0xC07F);          // operands in registers before the interleaved region
+#pragma unroll
+  for (int r = 0; r < 4; ++r) In[r] = op.I[r];
   __builtin_amdgcn_sched_barrier(0);
-  // gathers double-buffered: those of segment r are issued before waiting for
-  // those of segment r-1 (lgkmcnt(TPL): only LDS reads are outstanding here)
-  typename Elem<PT>::raw_t v[2][TPL];
+  // Gathers of DEPTH segments in flight: those of segment r are issued before
+  // waiting for those of segment r - DEPTH (lgkmcnt(DEPTH * TPL): only LDS
+  // reads are outstanding here, and lgkmcnt counts at most 15).  Two pay up
+  // to K = 8 (1 % at K = 8); at K = 16 the spilling kernel is 0.3 % slower.
+  constexpr int DEPTH = (KG <= 2 && 2 * TPL < 16) ? 2 : 1;
+  constexpr int NV = DEPTH + 1;
+  typename Elem<PT>::raw_t v[NV][TPL];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const BufConst bc = buffer_consts<PT>(p, lds, half, r);
@@ -212,30 +233,43 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
         addr[s] = E * (clamp_i32(bits, lo, hi) + cr);
       }
     }
-    if (r == 0) products_part<KG, TPL, 0>(ua, phi, pc, dn);
-    if (r == 1) products_part<KG, TPL, 1>(ua, phi, pc, dn);
-    if (r == 2) products_part<KG, TPL, 2>(ua, phi, pc, dn);
-    if (r == 3) products_part<KG, TPL, 3>(ua, phi, pc, dn);
+    if (r == 0) products_part<KG, TPL, 0>(op.ua, op.phi, pc, dn);
+    if (r == 1) products_part<KG, TPL, 1>(op.ua, op.phi, pc, dn);
+    if (r == 2) products_part<KG, TPL, 2>(op.ua, op.phi, pc, dn);
+    if (r == 3) products_part<KG, TPL, 3>(op.ua, op.phi, pc, dn);
     interleave_products<NQ>();
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int s = 0; s < TPL; ++s) v[r & 1][s] = Elem<PT>::raw(addr[s]);
+    for (int s = 0; s < TPL; ++s) v[r % NV][s] = Elem<PT>::raw(addr[s]);
     __builtin_amdgcn_sched_barrier(0);
-    if (r > 0) {
-      __builtin_amdgcn_s_waitcnt(0xC07F | (TPL << 8));   // lgkmcnt(TPL): gathers of segment r-1
+    if (r >= DEPTH) {
+      __builtin_amdgcn_s_waitcnt(0xC07F | ((DEPTH * TPL) << 8));   // gathers of segment r - DEPTH
       __builtin_amdgcn_sched_barrier(0);
-      if (r0 + r - 1 < p.n_seg) {
+      if (r0 + r - DEPTH < p.n_seg) {
 #pragma unroll
-        for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[(r - 1) & 1][s], p.one);
+        for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[(r - DEPTH) % NV][s], p.one);
       }
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  __builtin_amdgcn_s_waitcnt(0xC07F);
+  if constexpr (DEPTH == 2) {
+    __builtin_amdgcn_s_waitcnt(0xC07F | (TPL << 8));             // gathers of segment 2
+    __builtin_amdgcn_sched_barrier(0);
+    if (r0 + 2 < p.n_seg) {
+#pragma unroll
+      for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[2][s], p.one);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // operands of step r0 + 8 (any step in range past the end: loaded, unused)
+  const int rn = r0 + 8 < p.n_seg ? r0 + 8 : r0;
+  issue_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), rn, op);
+  __builtin_amdgcn_s_waitcnt(0xC07F);          // the last gathers and the operands
+  operands_landed<KG>(op);
   __builtin_amdgcn_sched_barrier(0);
   if (r0 + 3 < p.n_seg) {
 #pragma unroll
-    for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[1][s], p.one);
+    for (int s = 0; s < TPL; ++s) acc[s] = Elem<PT>::add(acc[s], v[3 % NV][s], p.one);
   }
   // FP32 runs of 8 segments (two steps), then FP64, as in the plain kernel
   if ((r0 & 4) != 0 || !more) {
@@ -263,16 +297,22 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, unsigned ch
   pipe_publish<PT>(p, pp, lds, 0);
   float4_t da[TPL], db[TPL];
   double Ia[4], Ib[4];
+  StepOps<KG> op;
   if (p.n_seg > 0) {
-    short4_t ua[3][KG];
-    float4_t phi;
-    step_operands<KG>(tab, reinterpret_cast<const MixedSeg *>(p.mseg), 0, ua, phi, Ia);
-    step_products<KG, TPL>(ua, phi, pc, da);
+    const MixedSeg *ms = reinterpret_cast<const MixedSeg *>(p.mseg);
+    issue_operands<KG>(tab, ms, 0, op);
+    step_products<KG, TPL>(op.ua, op.phi, pc, da);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ia[r] = op.I[r];
+    issue_operands<KG>(tab, ms, p.n_seg > 4 ? 4 : 0, op);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    operands_landed<KG>(op);
+    __builtin_amdgcn_sched_barrier(0);
   }
   for (int r0 = 0; r0 < p.n_seg; r0 += 8) {
-    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0, 0, da, Ia, db, Ib, acc, sum);
+    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0, 0, da, Ia, db, Ib, op, acc, sum);
     if (r0 + 4 >= p.n_seg) break;
-    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, da, Ia, acc, sum);
+    mixed_step<KG, TPL, PT, WILD>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, da, Ia, op, acc, sum);
   }
 }
 
