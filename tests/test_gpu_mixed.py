@@ -56,6 +56,29 @@ def test_mixed_exact_inputs_equal_plain(gpu_lib, K, dtype):
     assert np.max(np.abs(plain["stat"] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
 
 
+@pytest.mark.parametrize("K", [4, 8, 16])
+@pytest.mark.parametrize("n_seg", [1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12])
+def test_mixed_short_and_ragged_segment_counts(gpu_lib, K, n_seg):
+    """Every position of the last staging step (4 segments) and of the last
+    loop turn (two steps), with one and two segments of gathers in flight
+    (K = 4 and 16: one; K = 8: two); 14 workgroups of 500 templates each, so
+    the half-size tail tile and its idle lanes too."""
+    emri = gpu_lib
+    g = np.random.default_rng(1000 + 17 * K + n_seg)
+    n_bins, t = 600, 1.0
+    P = g.exponential(size=(n_seg, n_bins))
+    spec = emri.spectrogram_from_power(P, t, "f16")
+    f0 = np.round(g.uniform(200, 400, n_seg)) + 0.25
+    U = g.integers(-3, 4, (n_seg, K)).astype(np.float64)
+    C = (g.integers(-16, 17, (7000, K)) / 2.0).astype(np.float32)
+    plain = _score(emri, spec, f0, U, C, 16)
+    mixed = _score(emri, spec, f0, U, C, 16, precision="mixed")
+    assert np.array_equal(plain["stat"], mixed["stat"])
+    assert np.array_equal(plain["topk_idx"], mixed["topk_idx"])
+    o = oracle.score_tracks(_np(spec.power()).astype(np.float64), f0, U, C, t, 0)
+    assert np.max(np.abs(mixed["stat"] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
+
+
 def test_mixed_three_piece_split_beats_one_piece(gpu_lib):
     """Coefficients and U with 24 significant bits: a one-piece (plain BF16) product
     would move most tracks by many bins; the split keeps almost every bin."""
