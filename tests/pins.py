@@ -356,3 +356,49 @@ def check_score_range(score_tracks):
     got = score_tracks(P, f0, U, C, t_sft, 0, k_min=6, k_max=30, want_bins=True)
     assert list(got["stat"]) == [1.0, 0.0, 0.0, 2.0]
     assert list(got["bins"][3]) == [6, 21, -1]
+
+
+# ------------------------------------------------------------- checker helpers
+# Two oracle helpers decide which GPU rows a parity test accepts: the near-tie
+# band (either neighbouring bin is correct inside it) and the correctly rounded
+# segment sum at given bins (the statistic a GPU row is held to).
+
+
+def check_near_tie_band(near_tie_mask):
+    """Flagged iff |x - floor(x) - 1/2| < 1e-6; never for NaN or +-inf."""
+    inside, outside = 0.9e-6, 1.1e-6
+    for base in (0.0, 3.0, 117.0, 8000.0, 8192.0, -5.0, -1.0):
+        half = base + 0.5
+        x = np.array([half, half + inside, half - inside, half + outside, half - outside,
+                      base, base + 0.25, base + 0.75])
+        got = np.asarray(near_tie_mask(x))
+        assert got.dtype == bool
+        assert list(got) == [True, True, True, False, False, False, False, False], (base, got)
+    x = np.array([np.nan, np.inf, -np.inf, 0.5])
+    assert list(np.asarray(near_tie_mask(x))) == [False, False, False, True]
+
+
+def check_fsum_rows(fsum_rows):
+    """Correctly rounded sum over the contributing segments (bin -1: none)."""
+    from fractions import Fraction
+    g = np.random.default_rng(41)
+    n_seg, n_bins = 7, 20
+    P = g.uniform(0.0, 1.0, (n_seg, n_bins))
+    P[:, -1] = 1e3                       # a -1 bin read as an index would pick these up
+    P[0, 3] = 1e16                       # 1e16 + 1 + 1: naive left-to-right sums lose both ones
+    P[1, 4] = 1.0
+    P[2, 5] = 1.0
+    bins = g.integers(0, n_bins - 1, (6, n_seg))
+    bins[0, :3] = [3, 4, 5]
+    bins[0, 3:] = -1
+    bins[1, ::2] = -1
+    bins[2] = -1
+    got = np.asarray(fsum_rows(P, bins))
+    assert got.shape == (bins.shape[0],)
+    for j in range(bins.shape[0]):
+        want = Fraction(0)
+        for a in range(n_seg):
+            if bins[j, a] >= 0:
+                want += Fraction(float(P[a, bins[j, a]]))
+        assert got[j] == float(want), (j, got[j], float(want))
+    assert got[0] == 1e16 + 2.0 and got[2] == 0.0

@@ -75,6 +75,15 @@ def test_score_range_and_nonfinite():
     pins.check_score_range(oracle.score_tracks)
 
 
+def test_near_tie_band():
+    pins.check_near_tie_band(oracle.near_tie_mask)
+
+
+def test_fsum_rows():
+    from oracle.score import fsum_rows
+    pins.check_fsum_rows(fsum_rows)
+
+
 def test_oracle_is_isolated():
     """The oracle imports nothing from the HIP library package."""
     import ast, pathlib

@@ -169,3 +169,50 @@ def test_score_mutant_caught(name, monkeypatch):
     attr, fn = SCORE_MUTANTS[name]
     monkeypatch.setattr(osc, attr, fn)
     assert _caught(SCORE_PINS, osc.score_tracks), name
+
+
+# The checker helpers: a band wider than 1e-6 would excuse real bin errors; a
+# sum that counts non-contributing (-1) bins or rounds naively would hold GPU
+# rows to a wrong statistic.
+def _fsum_counts_invalid(P, bins):
+    P = np.asarray(P, dtype=np.float64)
+    return np.array([sum(P[a, b] for a, b in enumerate(row)) for row in bins])
+
+
+def _fsum_naive(P, bins):
+    P = np.asarray(P, dtype=np.float64)
+    out = np.zeros(bins.shape[0])
+    for j in range(bins.shape[0]):
+        acc = 0.0
+        for a, b in enumerate(bins[j]):
+            if b >= 0:
+                acc += P[a, b]
+        out[j] = acc
+    return out
+
+
+def _near_tie_closed_band(x):
+    finite = np.isfinite(x)
+    xs = np.where(finite, x, 0.0)
+    return finite & (np.abs(xs - np.floor(xs) - 0.5) <= osc.NEAR_TIE_BAND * 1.2)
+
+
+def _near_tie_nonfinite(x):
+    xs = np.nan_to_num(np.asarray(x, dtype=np.float64), nan=0.5, posinf=0.5, neginf=0.5)
+    return np.abs(xs - np.floor(xs) - 0.5) < osc.NEAR_TIE_BAND
+
+
+@pytest.mark.parametrize("band", [1e-3, 1e-5, 1e-7])
+def test_near_tie_band_mutant_caught(band, monkeypatch):
+    monkeypatch.setattr(osc, "NEAR_TIE_BAND", band)
+    assert _caught([pins.check_near_tie_band], osc.near_tie_mask), band
+
+
+@pytest.mark.parametrize("fn", [_near_tie_closed_band, _near_tie_nonfinite])
+def test_near_tie_mutant_caught(fn):
+    assert _caught([pins.check_near_tie_band], fn), fn.__name__
+
+
+@pytest.mark.parametrize("fn", [_fsum_counts_invalid, _fsum_naive])
+def test_fsum_rows_mutant_caught(fn):
+    assert _caught([pins.check_fsum_rows], fn), fn.__name__
