@@ -578,39 +578,4 @@ hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, i
   return dispatch_fast<__half>(K, p, grid, lds, stream, Ks{});
 }
 
-bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_max, int rows_per_step,
-                  size_t lds_limit, Staging *out) {
-  const int pitch_bytes = row_pitch * elem_bytes;
-  auto half_of = [&](int G) { return (size_t)SCORE_LDS_LEAD + round_up((size_t)G * pitch_bytes, 1024); };
-  auto fits = [&](int G) { return 2 * half_of(G) + SCORE_LDS_LEAD <= lds_limit; };
-  const bool padded = row_pitch > n_bins;      // a row's padding holds the next row's slot below bin 0
-  int G = 0;
-  if (rows_per_step != 0) {
-    if ((rows_per_step > 1 && !padded) || !fits(rows_per_step)) return false;
-    G = rows_per_step;
-  } else {
-    for (int g : {4, 2, 1})
-      if ((g == 1 || padded) && fits(g)) {
-        G = g;
-        break;
-      }
-    if (G == 0) return false;
-  }
-  const int half = (int)half_of(G);
-  const int copied = half - SCORE_LDS_LEAD;     // bytes a full step writes
-  uint64_t owner = ~0ull;
-  for (int j = 0; j < 2 * G; ++j) {
-    const int bin = (j & 1) ? k_max + 1 : k_min - 1;
-    const int rel = (j >> 1) * pitch_bytes + elem_bytes * bin;
-    const uint64_t w = (rel >= 0 && rel < copied) ? (uint64_t)((rel >> 10) % SCORE_WAVES) : 0xffull;
-    owner = (owner & ~(0xffull << (8 * j))) | (w << (8 * j));
-  }
-  out->G = G;
-  out->pitch_bytes = pitch_bytes;
-  out->half_bytes = half;
-  out->slot_owner = owner;
-  out->lds = 2 * (size_t)half + SCORE_LDS_LEAD;
-  return true;
-}
-
 }  // namespace emri

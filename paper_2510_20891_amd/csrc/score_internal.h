@@ -6,13 +6,12 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "staging_geom.h"
+
 namespace emri {
 
-constexpr int SCORE_THREADS = 512;   // one persistent workgroup of 8 waves per CU
 constexpr int EMRI_MAX_K = 32;
 constexpr int EMRI_MAX_TOPK = 4096;
-constexpr int SCORE_LDS_LEAD = 16;   // bytes ahead of each LDS half's first row
-constexpr int SCORE_WAVES = SCORE_THREADS / 64;
 
 struct TopkState;
 
@@ -58,21 +57,7 @@ __host__ __device__ constexpr int mixed_groups(int K) { return (K + 3) / 4; }
 // bytes of the BF16 piece table per segment: 3 pieces x groups x 4 values x 2 bytes
 __host__ __device__ constexpr int mixed_row_bytes(int K) { return 3 * mixed_groups(K) * 8; }
 
-// LDS staging of spectrogram rows.  Two halves, each a 16-byte lead-in followed
-// by G consecutive rows exactly as they lie in HBM (pitch_bytes apart), copied
-// as one contiguous block in 1 KB wave chunks.  Zero slot j (j < 2G) belongs to
-// row buffer j/2: the bin below k_min (j even) or above k_max (j odd).
-struct Staging {
-  int G, pitch_bytes, half_bytes;
-  uint64_t slot_owner;
-  size_t lds;                 // bytes of dynamic LDS (both halves and a 16-byte tail)
-};
-
-// Staging geometry for one spectrogram and bin range.  G = rows_per_step if it
-// is nonzero, else the most of 4, 2, 1 that fit; G > 1 needs a padding element
-// after every row (row_pitch > n_bins).  Returns false if it does not fit.
-bool make_staging(int n_bins, int row_pitch, int elem_bytes, int k_min, int k_max, int rows_per_step,
-                  size_t lds_limit, Staging *out);
+// LDS staging of spectrogram rows: see staging_geom.h (Staging, make_staging).
 
 // A range of one stream's templates, scored by one workgroup of the batched
 // launch.  Workgroups claim items in table order through an atomic counter.

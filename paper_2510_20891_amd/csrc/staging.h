@@ -105,8 +105,7 @@ __device__ __forceinline__ Pipe pipe_init(const ScoreParams &p) {
   pp.slot_mine = false;
   pp.slot_off = 0;
   if (lane < 2 * p.G) {
-    const int bin = (lane & 1) ? p.k_max + 1 : p.k_min - 1;
-    pp.slot_off = kLeadIn + (lane >> 1) * p.pitch_bytes + E * bin;
+    pp.slot_off = kLeadIn + zero_slot_rel(lane, p.pitch_bytes, E, p.k_min, p.k_max);
     pp.slot_mine = (int)((p.slot_owner >> (8 * lane)) & 0xffu) == pp.wave;
   }
   return pp;
@@ -117,21 +116,14 @@ __device__ __forceinline__ Pipe pipe_init(const ScoreParams &p) {
 // bytes; what they write lands in the half's slack, which no gather reads.
 __device__ __forceinline__ void pipe_issue(const ScoreParams &p, const Pipe &pp, unsigned char *lds, int r0,
                                            int half) {
-  if (r0 >= p.n_seg) return;
-  const int rows = p.n_seg - r0 < p.G ? p.n_seg - r0 : p.G;
-  const int bytes = rows * p.pitch_bytes;
-  const int last = (bytes - 1) >> 10;
+  const int rows = step_rows(p.n_seg, r0, p.G);
+  if (rows == 0) return;
   const char *src = reinterpret_cast<const char *>(p.power) + (size_t)r0 * (size_t)p.pitch_bytes;
   unsigned char *dst = lds + half * p.half_bytes + kLeadIn;
-  for (int c = pp.wave; c < last; c += SCORE_WAVES)
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + c * 1024 + pp.lane_off),
-                                     (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
-  if ((last & (SCORE_WAVES - 1)) == pp.wave) {
-    const int lim = bytes - 16 - last * 1024;
-    const int off = pp.lane_off < lim ? pp.lane_off : lim;
-    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + last * 1024 + off),
-                                     (__attribute__((address_space(3))) void *)(dst + last * 1024), 16, 0, 0);
-  }
+  for_each_copy(pp.wave, pp.lane_off, rows * p.pitch_bytes, [&](int c, int src_off) {
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src + src_off),
+                                     (__attribute__((address_space(3))) void *)(dst + c * STAGE_CHUNK), 16, 0, 0);
+  });
 }
 
 // Wait for this wave's copies, re-zero the slots they overwrote in half `half`,
