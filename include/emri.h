@@ -12,10 +12,11 @@
  *   - Plain C types only.  Pointers documented as "device" point to GPU memory
  *     (for instance a PyTorch tensor's data_ptr()); "host" pointers to CPU memory.
  *   - Every buffer, including the scoring workspace, is allocated by the caller.
- *     The library never allocates device memory and never synchronises a stream:
- *     device calls only enqueue work on `hip_stream` (a hipStream_t; NULL is the
- *     default stream) and return.  Outputs are valid once the caller has
- *     synchronised that stream.
+ *     The library never allocates device memory.  Device calls only enqueue
+ *     work on `hip_stream` (a hipStream_t; NULL is the default stream) and
+ *     return without synchronising, except score_batched_plan (a set-up call
+ *     that waits for its own table copies).  Outputs are valid once the caller
+ *     has synchronised that stream.
  *   - Every call returns an emri_status.  Arguments are validated before any HIP
  *     call; on failure nothing is enqueued and emri_last_error() describes why.
  *     Nothing is thrown or aborted across the boundary.
@@ -182,11 +183,13 @@ int score_tracks(const emri_power *power, const double *f0, const double *U, int
  * Each template's statistic is summed in the same order as in score_tracks, so
  * every result is bit-for-bit the one a standalone score_tracks call gives.
  *
- * score_batched_plan validates the problems, splits their tiles of templates
- * into one contiguous share of near-equal work per workgroup (one workgroup
- * per compute unit), and writes the launch tables into the workspace with
- * asynchronous host-to-device copies on hip_stream (the host arrays are
- * consumed before the call returns).  score_batched_run only launches kernels
+ * score_batched_plan validates the problems, splits them into work items of
+ * one or two tiles of templates ordered by decreasing cost (workgroups claim
+ * them through a counter), and writes the launch tables into the workspace
+ * with host-to-device copies on hip_stream.  Unlike every other call it then
+ * waits for hip_stream to drain (the copies read host memory the call owns),
+ * so it must not be called while a graph is being captured on hip_stream.
+ * score_batched_run only launches kernels
  * that read those tables, so it may be captured into a HIP graph and replayed;
  * a replay re-reads the problems' current device inputs.  The plan stays valid
  * while the workspace and every problem buffer stay allocated.

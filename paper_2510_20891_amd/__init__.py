@@ -215,21 +215,41 @@ def score_tracks_workspace_size(spec: Spectrogram, K: int, n_tmpl: int, top_k: i
 
 
 class Workspace:
-    """A reusable device workspace that grows on demand."""
+    """A reusable device workspace that grows on demand.
+
+    Use one workspace per stream: two calls in flight at once must not share
+    one.  The buffer is allocated on the stream that uses it, so the caching
+    allocator never hands it (or a replaced, smaller one) to work on another
+    stream before that stream's queued kernels are done with it.
+    """
 
     def __init__(self):
         self.buf = None
+        self.stream = None
 
-    def get(self, nbytes: int, device):
+    def get(self, nbytes: int, device, stream=None):
         import torch
+        s = stream if stream is not None else torch.cuda.current_stream(device)
         if self.buf is None or self.buf.numel() < nbytes or self.buf.device != device:
-            self.buf = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+            with torch.cuda.stream(s):
+                self.buf = torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+            self.stream = s
+        elif self.stream is not None and s.cuda_stream != self.stream.cuda_stream:
+            # reused on another stream: keep it alive until that stream's work is done
+            self.buf.record_stream(s)
         base = self.buf.data_ptr()
         off = (-base) % 256
         return base + off, self.buf.numel() - off
 
 
-_default_ws = Workspace()
+_default_ws: dict = {}
+
+
+def default_workspace(device, stream=None) -> Workspace:
+    """The binding's own workspace for calls on `stream` (one per device and stream)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return _default_ws.setdefault((str(device), int(s.cuda_stream)), Workspace())
 
 
 def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: bool = True,
@@ -253,25 +273,28 @@ def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: boo
     if coeffs.dim() != 2 or coeffs.shape[1] != K:
         raise ValueError("coeffs must be (n_tmpl, K)")
     dev = coeffs.device
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
     out = {} if out is None else out
     res = {}
-    if want_stat:
-        res["stat"] = out.get("stat") if out.get("stat") is not None else torch.empty(n_tmpl, dtype=torch.float32, device=dev)
-    res["topk_val"] = out.get("topk_val") if out.get("topk_val") is not None else torch.empty(top_k, dtype=torch.float32, device=dev)
-    res["topk_idx"] = out.get("topk_idx") if out.get("topk_idx") is not None else torch.empty(top_k, dtype=torch.int64, device=dev)
-    if want_bins:
-        res["bins"] = torch.empty((n_tmpl, spec.n_seg), dtype=torch.int32, device=dev)
-    if want_near_tie:
-        res["n_near_tie"] = torch.zeros(2, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(s):       # outputs belong to the stream that writes them
+        if want_stat:
+            res["stat"] = out.get("stat") if out.get("stat") is not None else torch.empty(n_tmpl, dtype=torch.float32, device=dev)
+        res["topk_val"] = out.get("topk_val") if out.get("topk_val") is not None else torch.empty(top_k, dtype=torch.float32, device=dev)
+        res["topk_idx"] = out.get("topk_idx") if out.get("topk_idx") is not None else torch.empty(top_k, dtype=torch.int64, device=dev)
+        if want_bins:
+            res["bins"] = torch.empty((n_tmpl, spec.n_seg), dtype=torch.int32, device=dev)
+        if want_near_tie:
+            res["n_near_tie"] = torch.empty(1, dtype=torch.int64, device=dev)
     nbytes = score_tracks_workspace_size(spec, K, n_tmpl, top_k, not want_stat)
-    ws_ptr, ws_len = (workspace or _default_ws).get(nbytes, dev)
+    ws = workspace if workspace is not None else default_workspace(dev, s)
+    ws_ptr, ws_len = ws.get(nbytes, dev, s)
     opts = _Opts(int(k_min), int(k_max), _PRECISIONS[precision])
     pw = spec._struct()
     _check("score_tracks", load().score_tracks(
         ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, int(top_k),
         _ptr(res.get("stat")), _ptr(res["topk_val"]) if top_k else None,
         _ptr(res["topk_idx"]) if top_k else None, _ptr(res.get("bins")),
-        _ptr(res.get("n_near_tie")), ctypes.byref(opts), ws_ptr, ws_len, _stream(stream)))
+        _ptr(res.get("n_near_tie")), ctypes.byref(opts), ws_ptr, ws_len, int(s.cuda_stream)))
     return res
 
 
@@ -342,7 +365,7 @@ class BatchPlan:
                lib.score_batched_workspace_size(arr, len(self.problems), self.K, ctypes.byref(nbytes)))
         dev = self.problems[0].coeffs.device if self.problems else torch.device("cuda")
         self._ws = workspace or Workspace()
-        ws_ptr, ws_len = self._ws.get(int(nbytes.value), dev)
+        ws_ptr, ws_len = self._ws.get(int(nbytes.value), dev, stream)
         self.opts = _BatchOpts(int(rows_per_step), int(templates_per_lane), _PRECISIONS[precision])
         self._plan = _Plan()
         _check("score_batched_plan", lib.score_batched_plan(arr, len(self.problems), self.K, ctypes.byref(self.opts),
@@ -354,4 +377,4 @@ class BatchPlan:
 
 
 __all__ = ["Problem", "BatchPlan", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
-           "Spectrogram", "spectrogram_from_power", "Workspace", "EmriError", "F32", "F16", "LIB_PATH"]
+           "Spectrogram", "spectrogram_from_power", "Workspace", "default_workspace", "EmriError", "F32", "F16", "LIB_PATH"]

@@ -315,6 +315,10 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   copy(L.topk_jobs, topks.data(), sizeof(TopkJob) * topks.size());
   copy(L.topk_blocks, block_job.data(), sizeof(int32_t) * block_job.size());
   copy(L.items, items.data(), sizeof(BatchItem) * items.size());
+  // The tables are host vectors that go away when this call returns, and an
+  // asynchronous copy from pageable memory may still be reading them: wait for
+  // the copies (planning is a set-up step; score_batched_run never waits).
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched plan copies: %s", hipGetErrorString(err));
 
   PlanData pd{};

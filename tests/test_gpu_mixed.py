@@ -57,26 +57,30 @@ def test_mixed_exact_inputs_equal_plain(gpu_lib, K, dtype):
 
 
 @pytest.mark.parametrize("K", [4, 8, 16])
-@pytest.mark.parametrize("n_seg", [1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12])
-def test_mixed_short_and_ragged_segment_counts(gpu_lib, K, n_seg):
+@pytest.mark.parametrize("n_seg,n_tmpl", [(n, 7000) for n in (1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12)] +
+                         [(n, 1_600_000) for n in (1, 3, 5, 8, 11)])
+def test_mixed_short_and_ragged_segment_counts(gpu_lib, K, n_seg, n_tmpl):
     """Every position of the last staging step (4 segments) and of the last
-    loop turn (two steps), with one and two segments of gathers in flight
-    (K = 4 and 16: one; K = 8: two); 14 workgroups of 500 templates each, so
-    the half-size tail tile and its idle lanes too."""
+    loop turn (two steps); up to K = 8 the kernel keeps the gathers of two
+    segments in flight, at K = 16 one.  With 7000 templates the 14 workgroups
+    get 500 templates each, so only the half-size tail tile runs (with idle
+    lanes); with 1.6e6 templates each of the (up to 256) workgroups gets about
+    6250, so full tiles of TPL x 512 templates run before a ragged tail."""
     emri = gpu_lib
-    g = np.random.default_rng(1000 + 17 * K + n_seg)
+    g = np.random.default_rng(1000 + 17 * K + n_seg + n_tmpl)
     n_bins, t = 600, 1.0
     P = g.exponential(size=(n_seg, n_bins))
     spec = emri.spectrogram_from_power(P, t, "f16")
     f0 = np.round(g.uniform(200, 400, n_seg)) + 0.25
     U = g.integers(-3, 4, (n_seg, K)).astype(np.float64)
-    C = (g.integers(-16, 17, (7000, K)) / 2.0).astype(np.float32)
+    C = (g.integers(-16, 17, (n_tmpl, K)) / 2.0).astype(np.float32)
     plain = _score(emri, spec, f0, U, C, 16)
     mixed = _score(emri, spec, f0, U, C, 16, precision="mixed")
     assert np.array_equal(plain["stat"], mixed["stat"])
     assert np.array_equal(plain["topk_idx"], mixed["topk_idx"])
-    o = oracle.score_tracks(_np(spec.power()).astype(np.float64), f0, U, C, t, 0)
-    assert np.max(np.abs(mixed["stat"] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
+    rows = np.arange(n_tmpl) if n_tmpl <= 10000 else np.unique(np.r_[np.arange(0, n_tmpl, 331), n_tmpl - 1])
+    o = oracle.score_tracks(_np(spec.power()).astype(np.float64), f0, U, C[rows], t, 0)
+    assert np.max(np.abs(mixed["stat"][rows] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
 
 
 def test_mixed_three_piece_split_beats_one_piece(gpu_lib):
@@ -103,30 +107,44 @@ def test_mixed_three_piece_split_beats_one_piece(gpu_lib):
     assert np.mean(np.rint(x1) != np.rint(oracle.track_positions(f0, U, C, t))) > 0.3
 
 
-def test_mixed_one_year_full_size_error_report(gpu_lib):
-    """1e7 templates, K = 8, FP16 power: statistic error against the FP64 oracle (on the same
-    FP16 power) on sampled templates, and the top-100 overlap on the first 2e5 templates."""
+@pytest.mark.parametrize("K", [8, 16])
+def test_mixed_one_year_full_size_error_report(gpu_lib, K):
+    """The one-year stream at its full shape (1e7 templates uniform in the K-basis
+    box, FP16 power): the statistic error against the FP64 oracle (on the same
+    FP16 power) on 3e4 sampled templates, p99 <= 2e-3 with the maximum bounded
+    by one flipped bin (the FP32 accumulation can move a position that lies
+    within ~1e-3 bin of a half-integer to the neighbouring bin); and the top-100
+    overlap with the oracle's exact top-100, found by scoring with the oracle
+    the union of the plain and mixed top-2000 (the plain statistic is within
+    1e-5 of the oracle's, so that union holds the oracle's top-100)."""
     import torch
     emri = gpu_lib
     st = synth.stream_config1(stream=0)
-    f0, U, sv, lo, hi = oracle.build_basis(st["tracks"], 8)
+    f0, U, sv, lo, hi = oracle.build_basis(st["tracks"], K)
     n = st["n_tmpl"]
-    C = synth.coefficients(1, 0, n, lo, hi)
+    C = synth.coefficients(1, K, n, lo, hi)
     spec = emri.build_sfts(_t(st["x"]), st["dt"], st["n_sft"], _t(st["psd"]), dtype="f16")
-    res = emri.score_tracks(spec, _t(f0), _t(U), _t(C), 0, precision="mixed")
+    C_d = _t(C)
+    res = emri.score_tracks(spec, _t(f0), _t(U), C_d, 100, precision="mixed")
+    plain = emri.score_tracks(spec, _t(f0), _t(U), C_d, 100)
     torch.cuda.synchronize()
     stat = _np(res["stat"])
     P16 = _np(spec.power()).astype(np.float64)
-    rows = np.random.default_rng(3).integers(0, n, 30000)
+    rows = np.random.default_rng(3 + K).integers(0, n, 30000)
     o = oracle.score_tracks(P16, f0, U, C[rows], spec.t_sft, 0)
     rel = np.abs(stat[rows] - o["stat"]) / np.abs(o["stat"])
-    assert np.quantile(rel, 0.99) <= 2e-3, np.quantile(rel, [0.5, 0.99, 1.0])
-    m = 200_000
-    o2 = oracle.score_tracks(P16, f0, U, C[:m], spec.t_sft, 100)
-    sub = emri.score_tracks(spec, _t(f0), _t(U), _t(C[:m]), 100, precision="mixed")
-    torch.cuda.synchronize()
-    overlap = len(set(_np(sub["topk_idx"]).tolist()) & set(o2["topk_idx"].tolist()))
+    q = np.quantile(rel, [0.5, 0.99, 1.0])
+    print(f"mixed K={K}: statistic relative error p50 {q[0]:.2e} p99 {q[1]:.2e} max {q[2]:.2e}")
+    assert q[1] <= 2e-3, q
+    assert q[2] <= 0.1, q
+    cand = np.unique(np.concatenate([_np(torch.topk(res["stat"], 2000).indices),
+                                     _np(torch.topk(plain["stat"], 2000).indices)]))
+    oc = oracle.score_tracks(P16, f0, U, C[cand], spec.t_sft, 100)
+    true_top = set(cand[oc["topk_idx"]].tolist())
+    overlap = len(true_top & set(_np(res["topk_idx"]).tolist()))
+    print(f"mixed K={K}: top-100 overlap {overlap}")
     assert overlap >= 99
+    assert np.array_equal(_np(res["topk_val"]), stat[_np(res["topk_idx"])])
 
 
 def test_mixed_batched_equals_standalone(gpu_lib):

@@ -374,32 +374,47 @@ def test_topk_nan_and_negative(gpu_lib):
 
 
 def test_one_year_full_size_sampled(gpu_lib):
-    """1e7 templates at K=8 on the 1-year stream, checked on sampled templates and the top-k."""
+    """1e7 templates at K = 8 on the one-year stream, in the launch the benchmark
+    times: 2e4 sampled templates (plus the top-k and both ends) against the
+    oracle, with near-ties judged at the GPU's own bins (the validation kernel
+    re-scores the sampled rows with the same arithmetic and summation order and
+    must reproduce the full launch's statistics bit for bit); and the top-256
+    against the oracle's exact top-256 over every template whose GPU statistic
+    could reach it (all within 3e-5 of the GPU's 256th value, which contains the
+    oracle's top-256 because every statistic is within 1e-5 of the oracle's)."""
     import torch
     emri = gpu_lib
     st = synth.stream_config1(stream=0)
     f0, U, sv, lo, hi = oracle.build_basis(st["tracks"], st["K"])
-    n = st["n_tmpl"]
+    n, k = st["n_tmpl"], st["top_k"]
     C = synth.coefficients(1, 0, n, lo, hi)
     spec = emri.build_sfts(_t(st["x"]), st["dt"], st["n_sft"], _t(st["psd"]))
-    res = emri.score_tracks(spec, _t(f0), _t(U), _t(C), st["top_k"])
+    f0_d, U_d, C_d = _t(f0), _t(U), _t(C)
+    res = emri.score_tracks(spec, f0_d, U_d, C_d, k)
     torch.cuda.synchronize()
     stat = _np(res["stat"])
+    top_idx, top_val = _np(res["topk_idx"]), _np(res["topk_val"])
     P_gpu = _np(spec.power()).astype(np.float64)
     t = spec.t_sft
+    assert np.array_equal(top_val, stat[top_idx])
+
+    def rescore(rows):
+        val = emri.score_tracks(spec, f0_d, U_d, _t(C[rows]), 0, want_bins=True, want_near_tie=True)
+        torch.cuda.synchronize()
+        val = {key: _np(v) for key, v in val.items()}
+        assert np.array_equal(val["stat"], stat[rows])
+        o = oracle.score_tracks(P_gpu, f0, U, C[rows], t, 0, want_bins=True)
+        check_against_oracle(P_gpu, f0, U, C[rows], t, val, o)
+        return oracle.score.fsum_rows(P_gpu, val["bins"].astype(np.int64))
+
     g = np.random.default_rng(1)
-    rows = np.unique(np.concatenate([g.integers(0, n, 20000), _np(res["topk_idx"]), [0, n - 1]]))
-    o = oracle.score_tracks(P_gpu, f0, U, C[rows], t, 0, want_bins=True)
-    x = oracle.track_positions(f0, U, C[rows], t)
-    rel = np.abs(stat[rows] - o["stat"]) / np.abs(o["stat"])
-    near_rows = oracle.near_tie_mask(x).any(axis=1)
-    assert rel[~near_rows].max() <= STAT_RTOL
-    # the top-k is the exact top-k of the statistic vector
-    sv_, si_ = torch.sort(res["stat"], descending=True, stable=True)
-    kth = float(sv_[st["top_k"] - 1])
-    got = set(_np(res["topk_idx"]).tolist())
-    assert set(_np(si_[: st["top_k"]]).tolist()) == got or np.isclose(kth, float(sv_[st["top_k"]]))
-    assert np.array_equal(_np(res["topk_val"]), stat[_np(res["topk_idx"])])
+    rescore(np.unique(np.concatenate([g.integers(0, n, 20000), top_idx, [0, n - 1]])))
+    kth = float(top_val[k - 1])
+    cand = np.flatnonzero(stat >= kth - 3e-5 * abs(kth))
+    assert k <= cand.size < 200_000, cand.size
+    ref = np.full(n, -np.inf)
+    ref[cand] = rescore(cand)
+    check_topk(top_val, top_idx, ref, k)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
@@ -437,3 +452,35 @@ def test_staging_geometries_with_dirty_padding(gpu_lib, dtype, n_seg, n_bins, pi
     o = oracle.score_tracks(P_used, f0, U, C, t, 16, k_min, k_max, want_bins=True)
     check_against_oracle(P_used, f0, U, C, t, val, o, k_min, k_max)
     assert fast["stat"].max() < 3.0e4 * 0.5
+
+
+def test_two_streams_in_flight_match_standalone(gpu_lib):
+    """Two calls queued on two streams at once, each with the binding's default
+    workspace for its stream: both results equal the same calls made alone."""
+    import torch
+    emri = gpu_lib
+    g = np.random.default_rng(77)
+    cases = []
+    for n_seg, n_bins, n in ((40, 3000, 300_000), (25, 5000, 200_000)):
+        t = 2000.0
+        P = g.exponential(size=(n_seg, n_bins))
+        spec = emri.spectrogram_from_power(P, t, "f32")
+        f0 = g.uniform(0.3, 0.7, n_seg) * n_bins / t
+        U = g.standard_normal((n_seg, 8)) * (40.0 / t)
+        C = g.uniform(-3, 3, (n, 8)).astype(np.float32)
+        cases.append((spec, _t(f0), _t(U), _t(C)))
+    alone = []
+    for spec, f0, U, C in cases:
+        r = emri.score_tracks(spec, f0, U, C, 64)
+        torch.cuda.synchronize()
+        alone.append({k: v.clone() for k, v in r.items()})
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for s in streams:
+        s.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for rep in range(3):
+        outs = [emri.score_tracks(*cases[i], 64, stream=streams[i]) for i in range(2)]
+    torch.cuda.synchronize()
+    for got, ref in zip(outs, alone):
+        for key in ("stat", "topk_val", "topk_idx"):
+            assert torch.equal(got[key], ref[key]), key
