@@ -173,6 +173,28 @@ int score_tracks(const emri_power *power, const double *f0, const double *U, int
                  void *workspace, size_t workspace_bytes, void *hip_stream);
 
 /*
+ * score_tracks_noalloc -- score_tracks for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, arithmetic, kernels and results as
+ * score_tracks, without the workspace: the library keeps a fixed scratch of
+ * score_tracks_noalloc_limit() bytes (4 MiB) per GPU in static device memory,
+ * held until the process ends, and this call allocates nothing.  A request
+ * whose workspace (score_tracks_workspace_size with stat_in_workspace = (stat
+ * == NULL)) exceeds that limit fails with EMRI_ENOMEM before any HIP call;
+ * one-year shapes with any top_k need about 0.3 MB when stat is given.
+ * Every call on a GPU uses that GPU's one scratch: calls that overlap on one
+ * GPU (concurrent streams, or threads) race and must be serialised by the
+ * caller.  Each call re-initialises what it reads from the scratch.
+ */
+int score_tracks_noalloc(const emri_power *power, const double *f0, const double *U, int32_t K,
+                         const float *coeffs, int64_t n_tmpl, int32_t top_k,
+                         float *stat, float *topk_val, int64_t *topk_idx,
+                         int32_t *bins, int64_t *n_near_tie, const score_opts *opts, void *hip_stream);
+
+/* Bytes of the static scratch score_tracks_noalloc uses on each GPU. */
+size_t score_tracks_noalloc_limit(void);
+
+/*
  * Batched form: many scoring problems in one persistent launch.
  *
  * A problem is one batch of coefficient vectors scored against one

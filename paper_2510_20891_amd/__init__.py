@@ -71,6 +71,9 @@ SIGNATURES = {
                                                    ctypes.POINTER(_sz)]),
     "score_tracks": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp,
                                     _vp, _vp, ctypes.POINTER(_Opts), _vp, _sz, _vp]),
+    "score_tracks_noalloc": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp,
+                                            _vp, _vp, ctypes.POINTER(_Opts), _vp]),
+    "score_tracks_noalloc_limit": (_sz, []),
     "score_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_sz)]),
     "score_batched_tile_options": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "score_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp,
@@ -298,6 +301,34 @@ def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: boo
     return res
 
 
+def score_tracks_noalloc(spec: Spectrogram, f0, U, coeffs, top_k: int, stat, topk_val, topk_idx, *,
+                         k_min: int = 0, k_max: int = -1, precision: str = "plain", stream=None) -> None:
+    """score_tracks into caller-owned outputs with the library's static scratch (no allocation).
+
+    ``stat`` (n_tmpl,) float32 or None, ``topk_val`` (top_k,) float32 and
+    ``topk_idx`` (top_k,) int64 are device tensors the caller owns.  Calls that
+    overlap on one GPU race on the shared scratch.
+    """
+    import torch
+    _require_cuda(f0, torch.float64, "f0")
+    _require_cuda(U, torch.float64, "U")
+    _require_cuda(coeffs, torch.float32, "coeffs")
+    K = int(U.shape[1]) if U.dim() == 2 else 0
+    n_tmpl = int(coeffs.shape[0])
+    if coeffs.dim() != 2 or coeffs.shape[1] != K:
+        raise ValueError("coeffs must be (n_tmpl, K)")
+    opts = _Opts(int(k_min), int(k_max), _PRECISIONS[precision])
+    pw = spec._struct()
+    _check("score_tracks_noalloc", load().score_tracks_noalloc(
+        ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, int(top_k),
+        _ptr(stat), _ptr(topk_val) if top_k else None, _ptr(topk_idx) if top_k else None, None, None,
+        ctypes.byref(opts), _stream(stream)))
+
+
+def score_tracks_noalloc_limit() -> int:
+    return int(load().score_tracks_noalloc_limit())
+
+
 @dataclass
 class Problem:
     """One scoring problem of a batched launch (device tensors; outputs allocated if None)."""
@@ -376,5 +407,5 @@ class BatchPlan:
         _check("score_batched_run", load().score_batched_run(ctypes.byref(self._plan), _stream(stream)))
 
 
-__all__ = ["Problem", "BatchPlan", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+__all__ = ["Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
            "Spectrogram", "spectrogram_from_power", "Workspace", "default_workspace", "EmriError", "F32", "F16", "LIB_PATH"]

@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "score_internal.h"
@@ -78,11 +79,65 @@ extern "C" int score_tracks_workspace_size(const emri_power *power, int32_t K, i
   return EMRI_OK;
 }
 
+namespace {
+
+// Scratch of score_tracks_noalloc: one copy per GPU, in the code object's
+// device memory, held until the process ends.  Its address on a device comes
+// from hipGetSymbolAddress with that device current (the array's name in host
+// code is only a host-side stand-in).  Calls on one device share it.
+constexpr size_t kNoallocScratchBytes = (size_t)4 << 20;
+__device__ __attribute__((aligned(256))) unsigned char scratch[kNoallocScratchBytes];
+
+int scratch_address(void **out) {
+  static std::mutex mu;
+  static void *addr[64] = {nullptr};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(EMRI_EDEVICE, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    const hipError_t err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (err != hipSuccess || !p)
+      return fail(EMRI_EDEVICE, "static scratch of device %d: %s", dev, hipGetErrorString(err));
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return EMRI_OK;
+}
+
+int score_tracks_impl(const emri_power *power, const double *f0, const double *U, int32_t K, const float *coeffs,
+                      int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx, int32_t *bins,
+                      int64_t *n_near_tie, const score_opts *opts, void *workspace, size_t workspace_bytes,
+                      void *hip_stream, bool static_scratch);
+
+}  // namespace
+
 extern "C" int score_tracks(const emri_power *power, const double *f0, const double *U, int32_t K,
                             const float *coeffs, int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val,
                             int64_t *topk_idx, int32_t *bins, int64_t *n_near_tie, const score_opts *opts,
                             void *workspace, size_t workspace_bytes, void *hip_stream) {
   clear_error();
+  return score_tracks_impl(power, f0, U, K, coeffs, n_tmpl, top_k, stat, topk_val, topk_idx, bins, n_near_tie, opts,
+                           workspace, workspace_bytes, hip_stream, false);
+}
+
+extern "C" int score_tracks_noalloc(const emri_power *power, const double *f0, const double *U, int32_t K,
+                                    const float *coeffs, int64_t n_tmpl, int32_t top_k, float *stat,
+                                    float *topk_val, int64_t *topk_idx, int32_t *bins, int64_t *n_near_tie,
+                                    const score_opts *opts, void *hip_stream) {
+  clear_error();
+  return score_tracks_impl(power, f0, U, K, coeffs, n_tmpl, top_k, stat, topk_val, topk_idx, bins, n_near_tie, opts,
+                           nullptr, kNoallocScratchBytes, hip_stream, true);
+}
+
+extern "C" size_t score_tracks_noalloc_limit(void) { return kNoallocScratchBytes; }
+
+namespace {
+
+int score_tracks_impl(const emri_power *power, const double *f0, const double *U, int32_t K, const float *coeffs,
+                      int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx, int32_t *bins,
+                      int64_t *n_near_tie, const score_opts *opts, void *workspace, size_t workspace_bytes,
+                      void *hip_stream, bool static_scratch) {
   int st = check_sizes(power, K, n_tmpl, top_k);
   if (st) return st;
   int k_min = 0, k_max = power->n_bins - 1, precision = EMRI_PLAIN;
@@ -107,13 +162,16 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   if (!U && K > 0 && power->n_seg > 0) return fail(EMRI_EINVAL, "U is NULL");
   if (!coeffs && K > 0 && n_tmpl > 0) return fail(EMRI_EINVAL, "coeffs is NULL");
   if (top_k > 0 && (!topk_val || !topk_idx)) return fail(EMRI_EINVAL, "topk_val/topk_idx are NULL");
-  if (!workspace) return fail(EMRI_EINVAL, "workspace is NULL");
+  if (!static_scratch && !workspace) return fail(EMRI_EINVAL, "workspace is NULL");
   const void *ptrs[] = {power->data, f0, U, coeffs, stat, topk_val, topk_idx, bins, n_near_tie};
   for (const void *p : ptrs)
     if (p && !aligned16(p)) return fail(EMRI_EINVAL, "device pointers must be 16-byte aligned");
   if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
   Layout L;
   make_layout(power, K, n_tmpl, top_k, stat == nullptr, &L);
+  if (static_scratch && L.total > workspace_bytes)
+    return fail(EMRI_ENOMEM, "this call needs %zu bytes of scratch; the static scratch holds %zu (pass stat, or "
+                "use score_tracks with a workspace)", L.total, workspace_bytes);
   if (workspace_bytes < L.total)
     return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
 
@@ -135,6 +193,7 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   }
   int cus = 0;
   if ((st = device_cu_count(&cus)) != EMRI_OK) return st;
+  if (static_scratch && (st = scratch_address(&workspace)) != EMRI_OK) return st;
 
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   char *ws = reinterpret_cast<char *>(workspace);
@@ -215,3 +274,5 @@ extern "C" int score_tracks(const emri_power *power, const double *f0, const dou
   }
   return EMRI_OK;
 }
+
+}  // namespace

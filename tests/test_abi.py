@@ -221,3 +221,22 @@ def test_mixed_precision_validation():
                                   ctypes.byref(plan), None) == -5      # four rows per step only
     assert lib.score_batched_plan(arr, 1, 8, ctypes.byref(emri._BatchOpts(0, 0, 3)), FAKE, 1 << 30,
                                   ctypes.byref(plan), None) == -1
+
+
+def test_noalloc_limit_and_rejections():
+    """score_tracks_noalloc validates like score_tracks and refuses, before any
+    HIP call, a request whose workspace would not fit its static scratch."""
+    lib = emri.load()
+    limit = lib.score_tracks_noalloc_limit()
+    assert limit == 4 << 20
+    pw = _power(n_seg=192, n_bins=8193, pitch=8200)
+    call = lambda n, stat, K=8, top_k=256: lib.score_tracks_noalloc(
+        ctypes.byref(pw), FAKE, FAKE, K, FAKE, n, top_k, stat, FAKE, FAKE, None, None, None, None)
+    need = ctypes.c_size_t(0)
+    assert lib.score_tracks_workspace_size(ctypes.byref(pw), 8, 2_000_000, 256, 1, ctypes.byref(need)) == 0
+    assert need.value > limit
+    assert call(2_000_000, None) == -3                        # statistic in the scratch: too big
+    assert b"static scratch" in lib.emri_last_error()
+    assert call(33, FAKE, K=33) == -1
+    assert call(-1, FAKE) == -1
+    assert call(10, FAKE + 4) == -1
