@@ -14,7 +14,9 @@ Each function is the plain definition of one step, written from the paper:
                       coefficient box (Sec. II C, Eqs. (9)-(10));
 * ``score_tracks`` -- the semi-coherent statistic Eq. (6) in its nearest-bin
                       limit, summed over segments, plus the top-k selection of
-                      Sec. II D.
+                      Sec. II D;
+* ``search``       -- the population search of Sec. II D: seeding and the
+                      track-space differential-evolution step of Eq. (11).
 
 Every function is pinned by the CPU tests against closed forms, brute force on
 tiny inputs and distributional laws (see the test modules); none is marked
@@ -24,10 +26,11 @@ from .sft import build_sfts, hann_periodic, sft_bin_frequencies
 from .basis import build_basis, BOX_Q_LO, BOX_Q_HI
 from .score import (score_tracks, track_positions, chosen_bins, near_tie_mask,
                     topk_order, score_tracks_exact, NEAR_TIE_BAND)
+from . import search
 
 __all__ = [
     "build_sfts", "hann_periodic", "sft_bin_frequencies",
     "build_basis", "BOX_Q_LO", "BOX_Q_HI",
     "score_tracks", "track_positions", "chosen_bins", "near_tie_mask", "topk_order",
-    "score_tracks_exact", "NEAR_TIE_BAND",
+    "score_tracks_exact", "NEAR_TIE_BAND", "search",
 ]

@@ -18,9 +18,15 @@ is replaced by seeded stand-ins with the same structure:
 * coefficient vectors drawn uniformly inside the basis-projection box
   (Sec. II C, last paragraph; Sec. II D, initial population).
 
+* the random numbers a population search draws (Sec. II D): seed candidates
+  uniform in the box with initial frequencies uniform in a range, and for
+  every differential-evolution generation the two partner walkers and the
+  weight of each walker.
+
 Seeds: ``rng(cfg, stream, purpose)`` with purpose 0 = noise, 1 = injection
 parameters and phase, 2 = training tracks, 3 + 16*chunk = coefficient chunk
-``chunk``, 4 = request arrivals and sizes.
+``chunk``, 4 = request arrivals and sizes, 5 = search seeding draws,
+6 + 16*gen = the draws of search generation ``gen``.
 """
 from __future__ import annotations
 
@@ -36,6 +42,8 @@ PURPOSE_INJECTION = 1
 PURPOSE_TRAINING = 2
 PURPOSE_COEFF = 3
 PURPOSE_REQUESTS = 4
+PURPOSE_SEARCH_SEED = 5
+PURPOSE_SEARCH_GEN = 6
 
 
 def rng(cfg: int, stream: int, purpose: int) -> np.random.Generator:
@@ -278,3 +286,32 @@ def device_coefficients(cfg: int, stream: int, n: int, box_lo, box_hi, device="c
         u = torch.rand((m, lo.numel()), dtype=torch.float64, device=device, generator=gen)
         out[s:s + m] = (lo + u * (hi - lo)).to(torch.float32)
     return out
+
+
+# ----------------------------------------------------------------- search draws
+def search_seed_draws(cfg: int, chain: int, n: int, box_lo, box_hi, f_lo: float = 5e-4, f_hi: float = 1e-2):
+    """Seed candidates of one search chain: coefficient vectors uniform in the
+    box (drawn in FP64, stored FP32) and initial frequencies uniform in
+    [f_lo, f_hi] Hz (FP64)."""
+    g = rng(cfg, chain, PURPOSE_SEARCH_SEED)
+    lo = np.asarray(box_lo, dtype=np.float64)
+    hi = np.asarray(box_hi, dtype=np.float64)
+    c = (lo[None, :] + (hi - lo)[None, :] * g.random((n, lo.size))).astype(np.float32)
+    return c, g.uniform(f_lo, f_hi, n)
+
+
+def search_generation_draws(cfg: int, chain: int, gen: int, n: int, f_lo: float = 0.3, f_hi: float = 1.5):
+    """Partners and weights of one differential-evolution generation: for every
+    walker i two other walkers r1 != r2 (uniform over the walkers other than i,
+    then over those other than i and r1) and a weight F uniform in [f_lo, f_hi]."""
+    if n < 3:
+        raise ValueError("a generation needs at least three walkers")
+    g = rng(cfg, chain, PURPOSE_SEARCH_GEN + 16 * gen)
+    i = np.arange(n)
+    r1 = (i + 1 + g.integers(0, n - 1, n)) % n
+    u = g.integers(0, n - 2, n)
+    a, b = np.minimum(i, r1), np.maximum(i, r1)
+    r2 = u + (u >= a)
+    r2 = r2 + (r2 >= b)
+    F = g.uniform(f_lo, f_hi, n)
+    return r1.astype(np.int32), r2.astype(np.int32), F

@@ -84,6 +84,30 @@ def test_fsum_rows():
     pins.check_fsum_rows(fsum_rows)
 
 
+def test_search_de_trial_closed_form():
+    import oracle.search as osr
+    from tests import pins_search
+    pins_search.check_de_trial_closed_form(osr.de_trials)
+
+
+def test_search_seed_closed_form():
+    import oracle.search as osr
+    from tests import pins_search
+    pins_search.check_seed_closed_form(osr.seed_candidates)
+
+
+def test_search_de_acceptance():
+    import oracle.search as osr
+    from tests import pins_search
+    pins_search.check_de_acceptance(osr.de_generation)
+
+
+def test_search_seed_keeps_best():
+    import oracle.search as osr
+    from tests import pins_search
+    pins_search.check_seed_keeps_best(osr.seed_population)
+
+
 def test_oracle_is_isolated():
     """The oracle imports nothing from the HIP library package."""
     import ast, pathlib

@@ -216,3 +216,101 @@ def test_near_tie_mutant_caught(fn):
 @pytest.mark.parametrize("fn", [_fsum_counts_invalid, _fsum_naive])
 def test_fsum_rows_mutant_caught(fn):
     assert _caught([pins.check_fsum_rows], fn), fn.__name__
+
+
+# ---------------------------------------------------------------- search (Eq. (11))
+import oracle.search as osr
+from tests import pins_search
+
+SEARCH_PINS = [pins_search.check_de_trial_closed_form, pins_search.check_seed_closed_form,
+               pins_search.check_de_acceptance, pins_search.check_seed_keeps_best]
+
+
+def _search_caught(monkeypatch, attr, fn):
+    monkeypatch.setattr(osr, attr, fn)
+    targets = {pins_search.check_de_trial_closed_form: lambda: osr.de_trials,
+               pins_search.check_seed_closed_form: lambda: osr.seed_candidates,
+               pins_search.check_de_acceptance: lambda: osr.de_generation,
+               pins_search.check_seed_keeps_best: lambda: osr.seed_population}
+    for check, target in targets.items():
+        try:
+            check(target())
+        except (AssertionError, ValueError, IndexError):
+            return True
+    return False
+
+
+def _trials_sign(f0, U, coeffs, r1, r2, F):
+    return _orig_trials(f0, U, coeffs, r2, r1, F)
+
+
+def _trials_no_F(f0, U, coeffs, r1, r2, F):
+    return _orig_trials(f0, U, coeffs, r1, r2, np.ones_like(np.asarray(F, dtype=np.float64)))
+
+
+def _project_transpose(f0, U, tracks):
+    return (np.asarray(tracks) - np.asarray(f0)[None, :]) @ np.asarray(U)
+
+
+def _in_prior_strict(coeffs, lo, hi):
+    c = np.asarray(coeffs, dtype=np.float32).astype(np.float64)
+    return np.all((c > np.asarray(lo)[None, :]) & (c < np.asarray(hi)[None, :]), axis=1)
+
+
+def _in_prior_always(coeffs, lo, hi):
+    return np.ones(np.asarray(coeffs).shape[0], dtype=bool)
+
+
+def _seed_last_segment(f0, U, draws, f_init):
+    f = osr.tracks_of(f0, U, draws)
+    moved = f + (np.asarray(f_init) - f[:, -1])[:, None]
+    return osr.project(f0, U, moved).astype(np.float32)
+
+
+def _seed_absolute(f0, U, draws, f_init):
+    f = osr.tracks_of(f0, U, draws)
+    return osr.project(f0, U, f + np.asarray(f_init)[:, None]).astype(np.float32)
+
+
+def _tracks_no_f0(f0, U, coeffs):
+    return np.asarray(coeffs, dtype=np.float32).astype(np.float64) @ np.asarray(U).T
+
+
+_orig_trials = osr.de_trials
+_orig_generation = osr.de_generation
+
+
+def _generation_ge(P, f0, U, lo, hi, coeffs, stat, r1, r2, F, t, k_min=0, k_max=None):
+    out = _orig_generation(P, f0, U, lo, hi, coeffs, stat, r1, r2, F, t, k_min, k_max)
+    acc = out["in_prior"] & (out["trial_stat"] >= np.asarray(stat))
+    out["accepted"] = acc
+    out["coeffs"] = np.where(acc[:, None], out["trial"], coeffs)
+    out["stat"] = np.where(acc, out["trial_stat"], stat)
+    return out
+
+
+def _keep_worst(P, f0, U, draws, f_init, t, n_keep, k_min=0, k_max=None):
+    cand = osr.seed_candidates(f0, U, draws, f_init)
+    st = osr.score_tracks(P, f0, U, cand, t, 0)["stat"]
+    idx = np.lexsort((np.arange(st.size), st))[:n_keep]
+    return cand[idx], st[idx], idx
+
+
+SEARCH_MUTANTS = {
+    "trial_sign": ("de_trials", _trials_sign),
+    "trial_no_F": ("de_trials", _trials_no_F),
+    "project_transpose": ("project", _project_transpose),
+    "prior_strict": ("in_prior", _in_prior_strict),
+    "prior_ignored": ("in_prior", _in_prior_always),
+    "seed_last_segment": ("seed_candidates", _seed_last_segment),
+    "seed_absolute": ("seed_candidates", _seed_absolute),
+    "tracks_no_f0": ("tracks_of", _tracks_no_f0),
+    "accept_ties": ("de_generation", _generation_ge),
+    "keep_worst": ("seed_population", _keep_worst),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SEARCH_MUTANTS))
+def test_search_mutant_caught(name, monkeypatch):
+    attr, fn = SEARCH_MUTANTS[name]
+    assert _search_caught(monkeypatch, attr, fn), name

@@ -68,3 +68,20 @@ def test_injection_recovered_tiny_stream():
     assert res["topk_idx"][0] == st["n_tmpl"]
     # random templates in the box look like noise on average
     assert abs(np.median(res["stat"][:-1]) - 30) < 5
+
+
+def test_search_draws():
+    lo, hi = np.array([-1.0, 0.0, 2.0]), np.array([1.0, 0.5, 3.0])
+    c, f = synth.search_seed_draws(0, 2, 1000, lo, hi)
+    assert c.dtype == np.float32 and c.shape == (1000, 3)
+    assert np.all(c >= lo.astype(np.float32)) and np.all(c <= hi.astype(np.float32))
+    assert np.all((f >= 5e-4) & (f <= 1e-2))
+    for n in (3, 4, 17, 512):
+        r1, r2, F = synth.search_generation_draws(0, 1, 3, n)
+        i = np.arange(n)
+        assert np.all((r1 != i) & (r2 != i) & (r1 != r2))
+        assert r1.min() >= 0 and r2.min() >= 0 and r1.max() < n and r2.max() < n
+        assert np.all((F >= 0.3) & (F <= 1.5))
+    a = synth.search_generation_draws(0, 1, 3, 64)
+    b = synth.search_generation_draws(0, 1, 4, 64)
+    assert not np.array_equal(a[0], b[0])            # generations draw independently
