@@ -98,3 +98,40 @@ def de_generation(P, f0, U, box_lo, box_hi, coeffs, stat, r1, r2, F, t_sft: floa
     new_c = np.where(accepted[:, None], trial, np.asarray(coeffs, dtype=np.float32))
     new_s = np.where(accepted, trial_stat, np.asarray(stat, dtype=np.float64))
     return dict(coeffs=new_c, stat=new_s, accepted=accepted, trial=trial, trial_stat=trial_stat, in_prior=inside)
+
+
+# ------------------------------------------------------- progressive durations
+# Sec. II D searches data of growing duration with the plunge at the end of
+# each: the one-year basis is shifted by a whole number of segments, so that a
+# chain on the first n segments uses the basis rows of the last n segments;
+# each duration's best statistic is normalised by the mean and standard
+# deviation of the same search on noise-only data.  Readings: the standard
+# deviation is the sample one (denominator R - 1 over R realisations); the
+# best walker is the first by (-S, index) with NaN last.
+
+
+def shifted_basis(f0, U, n: int):
+    """Basis rows of the last n segments (the basis shifted by len(f0) - n segments)."""
+    f0 = np.asarray(f0, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64)
+    N = f0.size
+    if not 1 <= n <= N:
+        raise ValueError("duration outside the basis")
+    return f0[N - n:], U[N - n:]
+
+
+def noise_moments(best) -> tuple:
+    """Mean and sample standard deviation over realisations (axis 0) of each chain's best statistic."""
+    b = np.asarray(best, dtype=np.float64)
+    return b.mean(axis=0), b.std(axis=0, ddof=1)
+
+
+def normalised(stat, mean, sd):
+    return (np.asarray(stat, dtype=np.float64) - np.asarray(mean)) / np.asarray(sd)
+
+
+def best_walker(stat) -> int:
+    s = np.asarray(stat, dtype=np.float64)
+    key = np.where(np.isnan(s), -np.inf, s)
+    rank_nan = np.isnan(s).astype(np.int64)
+    return int(np.lexsort((np.arange(s.size), -key, rank_nan))[0])

@@ -126,3 +126,41 @@ def check_seed_keeps_best(seed_population):
     assert list(idx) == order
     assert np.array_equal(np.asarray(coeffs), cand[order])
     assert np.array_equal(np.asarray(stat), full[order])
+
+
+def check_shifted_basis(shifted_basis):
+    """A full-rank basis of tracks that end at the plunge: the last n rows,
+    with a track's own coefficients, rebuild that track's last n values."""
+    g = np.random.default_rng(54)
+    N, n_train = 40, 12
+    F = np.cumsum(g.uniform(0, 1e-4, (n_train, N)), axis=1) + g.uniform(1e-3, 5e-3, (n_train, 1))
+    f0 = F.mean(axis=0)
+    X = F - f0
+    _, _, vt = np.linalg.svd(X, full_matrices=False)
+    U = vt[:n_train].T
+    c = X @ U
+    for n in (1, 7, 25, N):
+        fs, Us = shifted_basis(f0, U, n)
+        assert fs.shape == (n,) and Us.shape == (n, U.shape[1])
+        assert np.allclose(fs[None, :] + c @ Us.T, F[:, N - n:], rtol=0, atol=1e-15)
+
+
+def check_noise_moments(noise_moments):
+    import statistics
+    g = np.random.default_rng(55)
+    best = g.normal(100.0, 3.0, (6, 5))
+    best[:, 2] = 7.0                                   # no spread
+    best[:, 3] = [0.0, 2.0, 0.0, 2.0, 0.0, 2.0]
+    mean, sd = noise_moments(best)
+    for c in range(best.shape[1]):
+        col = [float(v) for v in best[:, c]]
+        assert abs(mean[c] - statistics.fmean(col)) <= 1e-12 * abs(mean[c]) + 1e-15
+        assert abs(sd[c] - statistics.stdev(col)) <= 1e-12 * max(sd[c], 1.0)
+    assert sd[2] == 0.0 and abs(sd[3] - np.sqrt(1.2)) <= 1e-15
+
+
+def check_best_walker(best_walker):
+    assert best_walker([1.0, 3.0, 2.0, 3.0]) == 1                 # ties: lower index
+    assert best_walker([np.nan, -5.0, -7.0]) == 1                  # NaN ranks last
+    assert best_walker([np.nan, np.nan]) == 0
+    assert best_walker([-np.inf, -1e30]) == 1

@@ -108,6 +108,14 @@ def test_search_seed_keeps_best():
     pins_search.check_seed_keeps_best(osr.seed_population)
 
 
+def test_search_progressive_pieces():
+    import oracle.search as osr
+    from tests import pins_search
+    pins_search.check_shifted_basis(osr.shifted_basis)
+    pins_search.check_noise_moments(osr.noise_moments)
+    pins_search.check_best_walker(osr.best_walker)
+
+
 def test_oracle_is_isolated():
     """The oracle imports nothing from the HIP library package."""
     import ast, pathlib

@@ -314,3 +314,33 @@ SEARCH_MUTANTS = {
 def test_search_mutant_caught(name, monkeypatch):
     attr, fn = SEARCH_MUTANTS[name]
     assert _search_caught(monkeypatch, attr, fn), name
+
+
+def _shift_first_rows(f0, U, n):
+    return np.asarray(f0)[:n], np.asarray(U)[:n]
+
+
+def _moments_population(best):
+    b = np.asarray(best, dtype=np.float64)
+    return b.mean(axis=0), b.std(axis=0)
+
+
+def _best_nan_first(stat):
+    s = np.asarray(stat, dtype=np.float64)
+    return int(np.lexsort((np.arange(s.size), -np.nan_to_num(s, nan=np.inf)))[0])
+
+
+def _best_last_tie(stat):
+    s = np.asarray(stat, dtype=np.float64)
+    key = np.where(np.isnan(s), -np.inf, s)
+    return int(np.lexsort((-np.arange(s.size), -key))[0])
+
+
+@pytest.mark.parametrize("check,fn", [
+    (pins_search.check_shifted_basis, _shift_first_rows),
+    (pins_search.check_noise_moments, _moments_population),
+    (pins_search.check_best_walker, _best_nan_first),
+    (pins_search.check_best_walker, _best_last_tie),
+])
+def test_progressive_mutant_caught(check, fn):
+    assert _caught([check], fn), fn.__name__
