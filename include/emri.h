@@ -253,6 +253,94 @@ int score_batched_plan(const emri_problem *problems, int32_t n_problems, int32_t
 
 int score_batched_run(const emri_batch_plan *plan, void *hip_stream);
 
+/*
+ * Population search (Sec. II D): the walkers of a search are coefficient
+ * vectors in the prior box, seeded from uniform draws and improved by the
+ * track-space differential-evolution step of Eq. (11).  A chain is one
+ * population scored against one spectrogram and basis; many chains advance
+ * together (one batched scoring launch per generation), e.g. one per
+ * observed duration of the progressive search, whose basis is the one-year
+ * basis shifted by a whole number of segments (f0 and U pointing
+ * n_seg_full - n_seg rows in, so the track ends at the chosen plunge).
+ * Tracks are projected back onto a chain's basis rows with their
+ * pseudo-inverse, which the set-up calls compute on the host (FP64, singular
+ * values below 1e-15 of the largest dropped).  Random numbers (candidate
+ * draws, initial frequencies, partners, weights) are inputs.
+ */
+typedef struct {
+  emri_power power;          /* the chain's spectrogram rows (n_seg >= 1)                   */
+  const double *f0;          /* device FP64[n_seg]                                          */
+  const double *U;           /* device FP64[n_seg * K], finite                              */
+  const double *box_lo;      /* device FP64[K]: prior box of the coefficients, inclusive   */
+  const double *box_hi;      /* device FP64[K]                                              */
+  float *coeffs;             /* device FP32[n_walkers * K]: the walkers, updated in place  */
+  float *stat;               /* device FP32[n_walkers]: their statistics, updated in place */
+  int32_t n_walkers;         /* >= 3                                                        */
+  int32_t k_min, k_max;      /* contributing bin range; k_max < 0 means n_bins - 1         */
+  int32_t reserved;          /* must be zero                                                */
+} emri_chain;
+
+typedef struct {
+  int64_t opaque[40];        /* filled by search_plan; caller-owned, not interpreted        */
+} emri_search_plan;
+
+/*
+ * search_seed -- Sec. II D's initial population, for every chain: candidate j
+ * of chain c is draws[(c * n_draw + j) * K ...] (device FP32, uniform in the
+ * box); its track f = f0 + U c is moved by one constant so that its first
+ * segment is at f_init[c * n_draw + j] Hz (device FP64), projected back onto
+ * the basis with its pseudo-inverse (FP32), scored, and the chain's n_walkers best by (-S, index)
+ * (n_walkers <= min(n_draw, 4096)) become its walkers, with their statistics.
+ * opts selects the scoring precision and tile (as score_batched_plan).
+ * A set-up call: like score_batched_plan it waits for its table copies.
+ */
+int search_seed_workspace_size(const emri_chain *chains, int32_t n_chains, int32_t K, int32_t n_draw, size_t *bytes);
+int search_seed(const emri_chain *chains, int32_t n_chains, int32_t K, const float *draws, const double *f_init,
+                int32_t n_draw, const batch_opts *opts, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * search_plan / search_generation -- Eq. (11).  search_plan (a set-up call
+ * that waits for its table copies) writes the chains' tables and the trials'
+ * scoring plan into the workspace.  search_generation then, for every walker
+ * i of every chain (walkers of chain c numbered from the sum of the earlier
+ * chains' n_walkers in the concatenated draws):
+ *     f_trial = f_i + F[i] (f_r1[i] - f_r2[i])        (tracks in FP64)
+ *     c_trial = pinv(U) (f_trial - f0), stored FP32
+ * scores every trial (one batched launch), and replaces walker i by its trial
+ * if every c_trial[k] lies in [box_lo[k], box_hi[k]] and the trial's
+ * statistic is strictly higher.  r1, r2: device INT32 partner indices within
+ * the chain (walkers whose r1, r2, i are not three different walkers in range
+ * keep their vector); F: device FP64 weights; accepted: device INT32 (1 if
+ * replaced) or NULL.  search_generation only launches kernels: it may be
+ * captured into a HIP graph.  The plan stays valid while the workspace and
+ * the chains' buffers stay allocated.
+ */
+int search_workspace_size(const emri_chain *chains, int32_t n_chains, int32_t K, size_t *bytes);
+int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K, const batch_opts *opts,
+                void *workspace, size_t workspace_bytes, emri_search_plan *plan, void *hip_stream);
+int search_generation(const emri_search_plan *plan, const int32_t *r1, const int32_t *r2, const double *F,
+                      int32_t *accepted, void *hip_stream);
+
+/*
+ * search_best -- per chain, the best walker by (-S, index) (NaN ranks last):
+ * best_stat FP32[n_chains], best_idx INT32[n_chains]; and, if best_norm is
+ * given (FP64[n_chains]), its statistic normalised by the chain's noise-only
+ * mean and standard deviation (device FP64[n_chains] each), the per-duration
+ * normalisation of Sec. II D.
+ */
+int search_best(const emri_search_plan *plan, const double *noise_mean, const double *noise_std,
+                float *best_stat, int32_t *best_idx, double *best_norm, void *hip_stream);
+
+/*
+ * search_noise_moments -- Sec. II D normalises each duration's statistic by
+ * its mean and standard deviation under noise-only data: over n_real >= 2
+ * noise-only searches, best[r * n_chains + c] (device FP32) is chain c's best
+ * statistic in realisation r; mean and sd (device FP64[n_chains]) receive the
+ * mean and the sample standard deviation (denominator n_real - 1).
+ */
+int search_noise_moments(const float *best, int32_t n_real, int32_t n_chains, double *mean, double *sd,
+                         void *hip_stream);
+
 /* Human-readable name of a status code (static storage). */
 const char *emri_status_string(int status);
 

@@ -64,6 +64,15 @@ class _BatchOpts(ctypes.Structure):
 class _Plan(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_int64 * 24)]
 
+class _Chain(ctypes.Structure):
+    _fields_ = [("power", _Power), ("f0", _vp), ("U", _vp), ("box_lo", _vp), ("box_hi", _vp), ("coeffs", _vp),
+                ("stat", _vp), ("n_walkers", _i32), ("k_min", _i32), ("k_max", _i32), ("reserved", _i32)]
+
+
+class _SearchPlan(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_int64 * 40)]
+
+
 SIGNATURES = {
     "build_sfts": (ctypes.c_int, [_vp, _i64, _dbl, _i32, _vp, ctypes.POINTER(_Power), _vp]),
     "build_basis": (ctypes.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
@@ -79,6 +88,15 @@ SIGNATURES = {
     "score_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp,
                                           _sz, ctypes.POINTER(_Plan), _vp]),
     "score_batched_run": (ctypes.c_int, [ctypes.POINTER(_Plan), _vp]),
+    "search_seed_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Chain), _i32, _i32, _i32, ctypes.POINTER(_sz)]),
+    "search_seed": (ctypes.c_int, [ctypes.POINTER(_Chain), _i32, _i32, _vp, _vp, _i32, ctypes.POINTER(_BatchOpts),
+                                   _vp, _sz, _vp]),
+    "search_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Chain), _i32, _i32, ctypes.POINTER(_sz)]),
+    "search_plan": (ctypes.c_int, [ctypes.POINTER(_Chain), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp, _sz,
+                                   ctypes.POINTER(_SearchPlan), _vp]),
+    "search_generation": (ctypes.c_int, [ctypes.POINTER(_SearchPlan), _vp, _vp, _vp, _vp, _vp]),
+    "search_best": (ctypes.c_int, [ctypes.POINTER(_SearchPlan), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "search_noise_moments": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "emri_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "emri_last_error": (ctypes.c_char_p, []),
 }
@@ -407,5 +425,140 @@ class BatchPlan:
         _check("score_batched_run", load().score_batched_run(ctypes.byref(self._plan), _stream(stream)))
 
 
-__all__ = ["Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+@dataclass
+class Chain:
+    """One search population (device tensors): ``coeffs`` (n_walkers, K) float32 and
+    ``stat`` (n_walkers,) float32 are updated in place; f0 / U may be views of a
+    longer basis (the basis shifted by whole segments)."""
+    spec: Spectrogram
+    f0: "object"
+    U: "object"
+    box_lo: "object"
+    box_hi: "object"
+    coeffs: "object"
+    stat: "object"
+    k_min: int = 0
+    k_max: int = -1
+
+    @property
+    def n_walkers(self) -> int:
+        return int(self.coeffs.shape[0])
+
+
+def _chains_array(chains, K: int):
+    import torch
+    arr = (_Chain * max(1, len(chains)))()
+    for i, c in enumerate(chains):
+        for name, dt in (("f0", torch.float64), ("U", torch.float64), ("box_lo", torch.float64),
+                         ("box_hi", torch.float64), ("coeffs", torch.float32), ("stat", torch.float32)):
+            _require_cuda(getattr(c, name), dt, name)
+        if tuple(c.coeffs.shape) != (c.n_walkers, K) or tuple(c.U.shape) != (c.spec.n_seg, K):
+            raise ValueError("chain shapes do not match K and the spectrogram")
+        a = arr[i]
+        a.power = c.spec._struct()
+        a.f0, a.U, a.box_lo, a.box_hi = _ptr(c.f0), _ptr(c.U), _ptr(c.box_lo), _ptr(c.box_hi)
+        a.coeffs, a.stat = _ptr(c.coeffs), _ptr(c.stat)
+        a.n_walkers, a.k_min, a.k_max = c.n_walkers, int(c.k_min), int(c.k_max)
+    return arr
+
+
+def search_seed(chains: list, K: int, draws, f_init, precision: str = "plain", workspace=None, stream=None) -> None:
+    """Seed every chain's walkers from draws (n_chains * n_draw, K) float32 and
+    f_init (n_chains * n_draw,) float64 device tensors (see include/emri.h)."""
+    import torch
+    _require_cuda(draws, torch.float32, "draws")
+    _require_cuda(f_init, torch.float64, "f_init")
+    n_draw = int(f_init.shape[0]) // max(1, len(chains))
+    if draws.shape[0] != n_draw * len(chains) or f_init.shape[0] != n_draw * len(chains):
+        raise ValueError("draws and f_init must hold n_draw rows per chain")
+    arr = _chains_array(chains, K)
+    lib = load()
+    nb = ctypes.c_size_t(0)
+    _check("search_seed_workspace_size", lib.search_seed_workspace_size(arr, len(chains), int(K), n_draw,
+                                                                        ctypes.byref(nb)))
+    dev = draws.device
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    ws = workspace or Workspace()
+    ws_ptr, ws_len = ws.get(int(nb.value), dev, s)
+    opts = _BatchOpts(0, 0, _PRECISIONS[precision])
+    _check("search_seed", lib.search_seed(arr, len(chains), int(K), _ptr(draws), _ptr(f_init), n_draw,
+                                          ctypes.byref(opts), ws_ptr, ws_len, int(s.cuda_stream)))
+
+
+class SearchPlan:
+    """A planned population search over many chains (Eq. (11)).
+
+    ``generation(r1, r2, F)`` runs one differential-evolution generation on
+    every chain; it only launches kernels, so it can be captured into a HIP
+    graph.  r1, r2: int32 and F: float64 device tensors with one entry per
+    walker, chains concatenated in order.  Keep the plan, its chains and its
+    workspace alive while it is used."""
+
+    def __init__(self, chains: list, K: int, precision: str = "plain", rows_per_step: int = 0,
+                 templates_per_lane: int = 0, workspace=None, stream=None):
+        import torch
+        self.chains = list(chains)
+        self.K = int(K)
+        self._arr = _chains_array(self.chains, self.K)
+        self.n_walkers = sum(c.n_walkers for c in self.chains)
+        lib = load()
+        nb = ctypes.c_size_t(0)
+        _check("search_workspace_size", lib.search_workspace_size(self._arr, len(self.chains), self.K,
+                                                                  ctypes.byref(nb)))
+        dev = self.chains[0].coeffs.device
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        self._ws = workspace or Workspace()
+        ws_ptr, ws_len = self._ws.get(int(nb.value), dev, s)
+        self.opts = _BatchOpts(int(rows_per_step), int(templates_per_lane), _PRECISIONS[precision])
+        self._plan = _SearchPlan()
+        _check("search_plan", lib.search_plan(self._arr, len(self.chains), self.K, ctypes.byref(self.opts), ws_ptr,
+                                              ws_len, ctypes.byref(self._plan), int(s.cuda_stream)))
+
+    def generation(self, r1, r2, F, accepted=None, stream=None) -> None:
+        import torch
+        _require_cuda(r1, torch.int32, "r1")
+        _require_cuda(r2, torch.int32, "r2")
+        _require_cuda(F, torch.float64, "F")
+        for t in (r1, r2, F):
+            if t.numel() < self.n_walkers:
+                raise ValueError("r1, r2 and F need one entry per walker")
+        if accepted is not None:
+            _require_cuda(accepted, torch.int32, "accepted")
+            if accepted.numel() < self.n_walkers:
+                raise ValueError("accepted needs one entry per walker")
+        _check("search_generation", load().search_generation(ctypes.byref(self._plan), _ptr(r1), _ptr(r2), _ptr(F),
+                                                             _ptr(accepted), _stream(stream)))
+
+    def best(self, noise_mean=None, noise_std=None, stream=None) -> dict:
+        """Per chain: best statistic and walker index, and the normalised statistic if noise moments are given."""
+        import torch
+        dev = self.chains[0].coeffs.device
+        n = len(self.chains)
+        out = {"stat": torch.empty(n, dtype=torch.float32, device=dev),
+               "idx": torch.empty(n, dtype=torch.int32, device=dev)}
+        if noise_mean is not None:
+            _require_cuda(noise_mean, torch.float64, "noise_mean")
+            _require_cuda(noise_std, torch.float64, "noise_std")
+            out["norm"] = torch.empty(n, dtype=torch.float64, device=dev)
+        _check("search_best", load().search_best(ctypes.byref(self._plan), _ptr(noise_mean), _ptr(noise_std),
+                                                 _ptr(out["stat"]), _ptr(out["idx"]), _ptr(out.get("norm")),
+                                                 _stream(stream)))
+        return out
+
+
+def search_noise_moments(best, stream=None):
+    """Per-chain mean and sample standard deviation over noise-only searches:
+    best is a (n_real, n_chains) float32 device tensor; returns two float64
+    (n_chains,) device tensors."""
+    import torch
+    _require_cuda(best, torch.float32, "best")
+    n_real, n_chains = int(best.shape[0]), int(best.shape[1])
+    mean = torch.empty(n_chains, dtype=torch.float64, device=best.device)
+    sd = torch.empty(n_chains, dtype=torch.float64, device=best.device)
+    _check("search_noise_moments", load().search_noise_moments(_ptr(best), n_real, n_chains, _ptr(mean), _ptr(sd),
+                                                               _stream(stream)))
+    return mean, sd
+
+
+__all__ = ["Chain", "SearchPlan", "search_seed", "search_noise_moments", "Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
            "Spectrogram", "spectrogram_from_power", "Workspace", "default_workspace", "EmriError", "F32", "F16", "LIB_PATH"]

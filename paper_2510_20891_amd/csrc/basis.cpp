@@ -175,3 +175,35 @@ extern "C" int build_basis(const double *tracks, int64_t n_train, int32_t n_seg,
   }
   return EMRI_OK;
 }
+
+namespace emri {
+
+// Pseudo-inverse of the n x K row-major matrix U, written transposed: pt[a*K + k]
+// = pinv(U)[k, a].  One-sided Jacobi on U's columns gives U V = B with
+// orthogonal columns b_j of norms s_j, so U = B V^T and pinv(U) = V S^-2 B^T;
+// directions with s_j <= 1e-15 max s are dropped (rank-deficient U).
+void pseudo_inverse_t(const double *U, int n, int K, double *pt) {
+  std::vector<double> B((size_t)n * K);
+  for (int a = 0; a < n; ++a)
+    for (int k = 0; k < K; ++k) B[(size_t)k * n + a] = U[(size_t)a * K + k];
+  std::vector<double> V;
+  hestenes_jacobi(B, n, K, V);
+  std::vector<double> s2(K);
+  double smax = 0.0;
+  for (int j = 0; j < K; ++j) {
+    double q = 0.0;
+    for (int a = 0; a < n; ++a) q += B[(size_t)j * n + a] * B[(size_t)j * n + a];
+    s2[j] = q;
+    smax = std::max(smax, std::sqrt(q));
+  }
+  std::fill(pt, pt + (size_t)n * K, 0.0);
+  for (int j = 0; j < K; ++j) {
+    if (!(std::sqrt(s2[j]) > 1e-15 * smax)) continue;
+    for (int a = 0; a < n; ++a) {
+      const double w = B[(size_t)j * n + a] / s2[j];
+      for (int k = 0; k < K; ++k) pt[(size_t)a * K + k] += V[(size_t)j * K + k] * w;
+    }
+  }
+}
+
+}  // namespace emri

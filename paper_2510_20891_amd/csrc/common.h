@@ -19,4 +19,8 @@ inline size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 // Number of compute units of the current device (cached per device).
 int device_cu_count(int *out);
 
+// Pseudo-inverse of the n x K row-major matrix U, transposed (pt[a*K + k]);
+// host FP64 (basis.cpp).
+void pseudo_inverse_t(const double *U, int n, int K, double *pt);
+
 }  // namespace emri

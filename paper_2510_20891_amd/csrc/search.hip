@@ -1,0 +1,633 @@
+// Population search over basis coefficients (Sec. II D): seeding and the
+// track-space differential-evolution generation of Eq. (11), for many chains
+// at once (a chain is one population against one spectrogram and basis; the
+// progressive-duration search runs one chain per observed duration).
+//
+// One generation is three launches, all reading device tables written by
+// search_plan, so a generation (or many) can be captured into a HIP graph:
+//   1. de_trials_kernel: per walker (one lane each), the trial track
+//      f_trial = f + F (f_r1 - f_r2) is formed segment by segment in FP64
+//      (f = f0 + U c), and projected back onto the basis with its
+//      pseudo-inverse, c_trial = pinv(U) (f_trial - f0), stored as FP32 (a
+//      chain's basis rows are a time-shifted part of the one-year basis, no
+//      longer orthonormal; the plan computes each chain's pseudo-inverse on
+//      the host, FP64 one-sided Jacobi, and keeps it in the workspace);
+//   2. the batched scoring launch over every chain's trials (one persistent
+//      launch, score_batched_run);
+//   3. de_select_kernel: a trial inside the prior box (bounds included) whose
+//      statistic is strictly higher replaces the walker.
+// Walkers whose partner indices are out of range or not distinct keep their
+// current vector (their trial is never accepted).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+#include "score_internal.h"
+
+using namespace emri;
+
+namespace {
+
+constexpr uint32_t kSearchMagic = 0x45534348u;   // "ESCH"
+constexpr int kSearchThreads = 256;
+
+// One chain as the kernels see it (device table).
+struct ChainDesc {
+  const double *f0, *U, *box_lo, *box_hi;
+  const double *pinvt;             // pinv(U) transposed: n_seg x K (workspace)
+  float *coeffs, *stat;            // the walkers (updated in place)
+  float *trial, *trial_stat;       // this generation's trials (workspace)
+  int64_t offset;                  // first walker of the chain in the concatenated draws
+  int32_t n_seg, n_walkers;
+};
+
+// What search_generation needs, kept in the caller's emri_search_plan.
+struct SearchPlanData {
+  uint32_t magic;
+  int32_t n_chains;
+  int32_t K;
+  int32_t max_walkers;
+  const ChainDesc *chains;
+  emri_batch_plan scoring;
+};
+static_assert(sizeof(SearchPlanData) <= sizeof(emri_search_plan), "search plan does not fit");
+
+// f[alpha] of a walker (FP64): f0[alpha] + sum_k U[alpha, k] c_k
+template <int K>
+__device__ __forceinline__ double track_at(const double *f0, const double *Ua, const double (&c)[K], int alpha) {
+  double f = f0[alpha];
+#pragma unroll
+  for (int k = 0; k < K; ++k) f = __builtin_fma(Ua[k], c[k], f);
+  return f;
+}
+
+template <int K>
+__global__ __launch_bounds__(kSearchThreads) void de_trials_kernel(const ChainDesc *__restrict__ chains,
+                                                                   const int32_t *__restrict__ r1,
+                                                                   const int32_t *__restrict__ r2,
+                                                                   const double *__restrict__ F) {
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  const int i = blockIdx.x * kSearchThreads + threadIdx.x;
+  if (i >= ch.n_walkers) return;
+  const int64_t gi = ch.offset + i;
+  const int a = r1[gi], b = r2[gi];
+  const bool valid = a >= 0 && a < ch.n_walkers && b >= 0 && b < ch.n_walkers && a != i && b != i && a != b;
+  double ci[K], ca[K], cb[K], out[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ci[k] = (double)ch.coeffs[(size_t)i * K + k];
+    ca[k] = valid ? (double)ch.coeffs[(size_t)a * K + k] : ci[k];
+    cb[k] = valid ? (double)ch.coeffs[(size_t)b * K + k] : ci[k];
+    out[k] = 0.0;
+  }
+  const double w = valid ? F[gi] : 0.0;
+  for (int alpha = 0; alpha < ch.n_seg; ++alpha) {
+    const double *Ua = ch.U + (size_t)alpha * K;
+    const double fi = track_at<K>(ch.f0, Ua, ci, alpha);
+    const double fa = track_at<K>(ch.f0, Ua, ca, alpha);
+    const double fb = track_at<K>(ch.f0, Ua, cb, alpha);
+    const double d = __builtin_fma(w, fa - fb, fi) - ch.f0[alpha];     // f_trial - f0
+    const double *Pa = ch.pinvt + (size_t)alpha * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) ch.trial[(size_t)i * K + k] = valid ? (float)out[k] : __builtin_nanf("");
+}
+
+__global__ __launch_bounds__(kSearchThreads) void de_select_kernel(const ChainDesc *__restrict__ chains, int K,
+                                                                   int32_t *__restrict__ accepted) {
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  const int i = blockIdx.x * kSearchThreads + threadIdx.x;
+  if (i >= ch.n_walkers) return;
+  bool inside = true;
+  for (int k = 0; k < K; ++k) {
+    const double v = (double)ch.trial[(size_t)i * K + k];
+    inside &= v >= ch.box_lo[k] && v <= ch.box_hi[k];            // NaN: outside
+  }
+  const float s = ch.trial_stat[i];
+  const bool take = inside && s > ch.stat[i];
+  if (take) {
+    for (int k = 0; k < K; ++k) ch.coeffs[(size_t)i * K + k] = ch.trial[(size_t)i * K + k];
+    ch.stat[i] = s;
+  }
+  if (accepted) accepted[ch.offset + i] = take ? 1 : 0;
+}
+
+// Seeding: every candidate's track is moved by one constant so that its first
+// segment sits at f_init, then projected back (FP32 result).  Chain c's
+// candidates are draws[c * n_draw + j] (K values each); cand holds them at a
+// stride of cand_stride floats per chain.
+template <int K>
+__global__ __launch_bounds__(kSearchThreads) void seed_move_kernel(const ChainDesc *__restrict__ chains,
+                                                                   const float *__restrict__ draws,
+                                                                   const double *__restrict__ f_init, int n_draw,
+                                                                   float *__restrict__ cand, int64_t cand_stride) {
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  const int j = blockIdx.x * kSearchThreads + threadIdx.x;
+  if (j >= n_draw) return;
+  const int64_t gj = (int64_t)blockIdx.y * n_draw + j;
+  double c[K], out[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    c[k] = (double)draws[(size_t)gj * K + k];
+    out[k] = 0.0;
+  }
+  const double shift = f_init[gj] - track_at<K>(ch.f0, ch.U, c, 0);
+  for (int alpha = 0; alpha < ch.n_seg; ++alpha) {
+    const double *Ua = ch.U + (size_t)alpha * K;
+    const double d = (track_at<K>(ch.f0, Ua, c, alpha) + shift) - ch.f0[alpha];
+    const double *Pa = ch.pinvt + (size_t)alpha * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
+  }
+  float *dst = cand + (size_t)blockIdx.y * cand_stride + (size_t)j * K;
+#pragma unroll
+  for (int k = 0; k < K; ++k) dst[k] = (float)out[k];
+}
+
+// The n_walkers best candidates of each chain become its walkers.
+__global__ __launch_bounds__(kSearchThreads) void seed_gather_kernel(const ChainDesc *__restrict__ chains, int K,
+                                                                     const float *__restrict__ cand,
+                                                                     int64_t cand_stride,
+                                                                     const float *__restrict__ top_val,
+                                                                     const int64_t *__restrict__ top_idx,
+                                                                     int64_t top_stride) {
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  const int i = blockIdx.x * kSearchThreads + threadIdx.x;
+  if (i >= ch.n_walkers) return;
+  const int64_t slot = (int64_t)blockIdx.y * top_stride + i;
+  const int64_t j = top_idx[slot];                 // always a candidate: n_walkers <= n_draw
+  const float *src = cand + (size_t)blockIdx.y * cand_stride + (size_t)(j >= 0 ? j : 0) * K;
+  for (int k = 0; k < K; ++k) ch.coeffs[(size_t)i * K + k] = src[k];
+  ch.stat[i] = top_val[slot];
+}
+
+// a ranks above b in the order (-S, index) with NaN below every number
+__device__ __forceinline__ bool ranks_above(float va, int ia, float vb, int ib) {
+  if (ib < 0) return ia >= 0;
+  if (ia < 0) return false;
+  const bool na = va != va, nb = vb != vb;
+  if (na != nb) return nb;
+  if (!na && va != vb) return va > vb;
+  return ia < ib;
+}
+
+// Per chain: the best walker by (-S, index), and its statistic normalised by
+// the chain's noise-only mean and standard deviation.
+__global__ __launch_bounds__(kSearchThreads) void search_best_kernel(const ChainDesc *__restrict__ chains,
+                                                                     const double *__restrict__ noise_mean,
+                                                                     const double *__restrict__ noise_std,
+                                                                     float *__restrict__ best_stat,
+                                                                     int32_t *__restrict__ best_idx,
+                                                                     double *__restrict__ best_norm) {
+  __shared__ float sv[kSearchThreads];
+  __shared__ int si[kSearchThreads];
+  const ChainDesc ch = load_uniform(chains + blockIdx.x);
+  float v = 0.0f;
+  int idx = -1;
+  for (int i = threadIdx.x; i < ch.n_walkers; i += kSearchThreads) {
+    const float s = ch.stat[i];
+    if (ranks_above(s, i, v, idx)) {
+      v = s;
+      idx = i;
+    }
+  }
+  sv[threadIdx.x] = v;
+  si[threadIdx.x] = idx;
+  __syncthreads();
+  for (int off = kSearchThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off && ranks_above(sv[threadIdx.x + off], si[threadIdx.x + off], sv[threadIdx.x], si[threadIdx.x])) {
+      sv[threadIdx.x] = sv[threadIdx.x + off];
+      si[threadIdx.x] = si[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    best_stat[blockIdx.x] = sv[0];
+    best_idx[blockIdx.x] = si[0];
+    if (best_norm)
+      best_norm[blockIdx.x] = ((double)sv[0] - noise_mean[blockIdx.x]) / noise_std[blockIdx.x];
+  }
+}
+
+// Mean and sample standard deviation (n - 1 in the denominator) over n_real
+// realisations of each chain's best statistic; best[r * n_chains + c].
+__global__ __launch_bounds__(kSearchThreads) void noise_moments_kernel(const float *__restrict__ best, int n_real,
+                                                                       int n_chains, double *__restrict__ mean,
+                                                                       double *__restrict__ sd) {
+  const int c = blockIdx.x * kSearchThreads + threadIdx.x;
+  if (c >= n_chains) return;
+  double m = 0.0;
+  for (int r = 0; r < n_real; ++r) m += (double)best[(size_t)r * n_chains + c];
+  m /= n_real;
+  double q = 0.0;
+  for (int r = 0; r < n_real; ++r) {
+    const double d = (double)best[(size_t)r * n_chains + c] - m;
+    q += d * d;
+  }
+  mean[c] = m;
+  sd[c] = __builtin_sqrt(q / (n_real - 1));
+}
+
+template <int... Ks>
+hipError_t launch_trials(int K, dim3 grid, hipStream_t stream, const ChainDesc *chains, const int32_t *r1,
+                         const int32_t *r2, const double *F, std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  auto one = [&](auto kc) {
+    constexpr int KK = decltype(kc)::value;
+    hipLaunchKernelGGL(de_trials_kernel<KK>, grid, dim3(kSearchThreads), 0, stream, chains, r1, r2, F);
+    err = hipGetLastError();
+  };
+  ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}), true) : false) || ...);
+  return err;
+}
+
+template <int... Ks>
+hipError_t launch_seed_move(int K, dim3 grid, hipStream_t stream, const ChainDesc *chains, const float *draws,
+                            const double *f_init, int n_draw, float *cand, int64_t cand_stride,
+                            std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  auto one = [&](auto kc) {
+    constexpr int KK = decltype(kc)::value;
+    hipLaunchKernelGGL(seed_move_kernel<KK>, grid, dim3(kSearchThreads), 0, stream, chains, draws, f_init, n_draw,
+                       cand, cand_stride);
+    err = hipGetLastError();
+  };
+  ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}), true) : false) || ...);
+  return err;
+}
+
+using AllK = std::make_integer_sequence<int, EMRI_MAX_K>;
+
+int check_chain(const emri_chain &c, int i) {
+  if (c.n_walkers < 3) return fail(EMRI_EINVAL, "chain %d: n_walkers %d < 3", i, c.n_walkers);
+  if (c.reserved != 0) return fail(EMRI_EINVAL, "chain %d: reserved must be zero", i);
+  if (!c.f0 || !c.U || !c.box_lo || !c.box_hi || !c.coeffs || !c.stat)
+    return fail(EMRI_EINVAL, "chain %d: a required pointer is NULL", i);
+  const void *ptrs[] = {c.f0, c.U, c.box_lo, c.box_hi, c.coeffs, c.stat};
+  for (const void *p : ptrs)
+    if (!aligned16(p)) return fail(EMRI_EINVAL, "chain %d: device pointers must be 16-byte aligned", i);
+  if (c.power.n_seg < 1) return fail(EMRI_EINVAL, "chain %d: no segments", i);
+  return EMRI_OK;
+}
+
+struct SearchLayout {
+  size_t chains, trials, scoring, total;
+  std::vector<size_t> trial_off, tstat_off, pinv_off;
+};
+
+SearchLayout search_layout(const emri_chain *chains, int n, int K, size_t scoring_bytes) {
+  SearchLayout L;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes > 0 ? bytes : 1, 256);
+    return at;
+  };
+  L.chains = take(sizeof(ChainDesc) * (size_t)n);
+  L.trials = off;
+  for (int i = 0; i < n; ++i) {
+    L.trial_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers * K));
+    L.tstat_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers));
+    L.pinv_off.push_back(take(sizeof(double) * (size_t)chains[i].power.n_seg * K));
+  }
+  L.scoring = take(scoring_bytes);
+  L.total = off;
+  return L;
+}
+
+// The scoring problems of the trials: chain i's trial buffer against its spectrogram.
+std::vector<emri_problem> trial_problems(const emri_chain *chains, int n, char *ws, const SearchLayout &L) {
+  std::vector<emri_problem> pbs((size_t)n);
+  // sizing calls pass no workspace: any aligned non-null address stands in
+  char *base = ws ? ws : reinterpret_cast<char *>(256);
+  for (int i = 0; i < n; ++i) {
+    emri_problem &p = pbs[i];
+    std::memset(&p, 0, sizeof p);
+    p.power = chains[i].power;
+    p.f0 = chains[i].f0;
+    p.U = chains[i].U;
+    p.coeffs = reinterpret_cast<const float *>(base + L.trial_off[i]);
+    p.n_tmpl = chains[i].n_walkers;
+    p.top_k = 0;
+    p.k_min = chains[i].k_min;
+    p.k_max = chains[i].k_max;
+    p.stat = reinterpret_cast<float *>(base + L.tstat_off[i]);
+  }
+  return pbs;
+}
+
+int validate_chains(const emri_chain *chains, int32_t n_chains, int32_t K) {
+  if (!chains && n_chains > 0) return fail(EMRI_EINVAL, "chains is NULL");
+  if (n_chains < 1 || n_chains > 65535) return fail(EMRI_EINVAL, "n_chains %d outside [1, 65535]", n_chains);
+  if (K < 1 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K = %d outside [1, %d]", K, EMRI_MAX_K);
+  for (int i = 0; i < n_chains; ++i) {
+    const int st = check_chain(chains[i], i);
+    if (st) return st;
+  }
+  return EMRI_OK;
+}
+
+int scoring_bytes_for(const emri_chain *chains, int n, int K, size_t *bytes) {
+  SearchLayout L0 = search_layout(chains, n, K, 0);
+  std::vector<emri_problem> pbs = trial_problems(chains, n, nullptr, L0);
+  return score_batched_workspace_size(pbs.data(), n, K, bytes);
+}
+
+// Each chain's pseudo-inverse (transposed, n_seg x K) at dst + off[i]: its
+// basis rows are copied to the host, inverted there and copied back.  Waits
+// for the copies (set-up calls only).
+int upload_pinv(const emri_chain *chains, int n, int K, char *dst, const std::vector<size_t> &off,
+                hipStream_t stream) {
+  std::vector<std::vector<double>> pt((size_t)n);
+  std::vector<double> u;
+  for (int i = 0; i < n; ++i) {
+    const int ns = chains[i].power.n_seg;
+    u.resize((size_t)ns * K);
+    hipError_t err = hipMemcpyAsync(u.data(), chains[i].U, sizeof(double) * u.size(), hipMemcpyDeviceToHost, stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "chain %d: basis copy: %s", i, hipGetErrorString(err));
+    for (double v : u)
+      if (!std::isfinite(v)) return fail(EMRI_EINVAL, "chain %d: the basis holds a non-finite value", i);
+    pt[i].resize(u.size());
+    pseudo_inverse_t(u.data(), ns, K, pt[i].data());
+    err = hipMemcpyAsync(dst + off[i], pt[i].data(), sizeof(double) * pt[i].size(), hipMemcpyHostToDevice, stream);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "chain %d: pseudo-inverse copy: %s", i, hipGetErrorString(err));
+  }
+  const hipError_t err = hipStreamSynchronize(stream);      // pt holds the sources of the copies
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "pseudo-inverse copies: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}
+
+dim3 walker_grid(int max_walkers, int n_chains) {
+  return dim3((unsigned)((max_walkers + kSearchThreads - 1) / kSearchThreads), (unsigned)n_chains);
+}
+
+}  // namespace
+
+extern "C" int search_workspace_size(const emri_chain *chains, int32_t n_chains, int32_t K, size_t *bytes) {
+  clear_error();
+  if (!bytes) return fail(EMRI_EINVAL, "bytes is NULL");
+  int st = validate_chains(chains, n_chains, K);
+  if (st) return st;
+  size_t sb = 0;
+  if ((st = scoring_bytes_for(chains, n_chains, K, &sb)) != EMRI_OK) return st;
+  *bytes = search_layout(chains, n_chains, K, sb).total;
+  return EMRI_OK;
+}
+
+extern "C" int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K, const batch_opts *opts,
+                           void *workspace, size_t workspace_bytes, emri_search_plan *plan, void *hip_stream) {
+  clear_error();
+  if (!plan || !workspace) return fail(EMRI_EINVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
+  int st = validate_chains(chains, n_chains, K);
+  if (st) return st;
+  size_t sb = 0;
+  if ((st = scoring_bytes_for(chains, n_chains, K, &sb)) != EMRI_OK) return st;
+  const SearchLayout L = search_layout(chains, n_chains, K, sb);
+  if (workspace_bytes < L.total)
+    return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
+  char *ws = reinterpret_cast<char *>(workspace);
+  std::vector<ChainDesc> desc((size_t)n_chains);
+  int64_t offset = 0;
+  int max_walkers = 0;
+  for (int i = 0; i < n_chains; ++i) {
+    ChainDesc &d = desc[i];
+    std::memset(&d, 0, sizeof d);
+    d.f0 = chains[i].f0;
+    d.U = chains[i].U;
+    d.box_lo = chains[i].box_lo;
+    d.box_hi = chains[i].box_hi;
+    d.coeffs = chains[i].coeffs;
+    d.stat = chains[i].stat;
+    d.pinvt = reinterpret_cast<const double *>(ws + L.pinv_off[i]);
+    d.trial = reinterpret_cast<float *>(ws + L.trial_off[i]);
+    d.trial_stat = reinterpret_cast<float *>(ws + L.tstat_off[i]);
+    d.offset = offset;
+    d.n_seg = chains[i].power.n_seg;
+    d.n_walkers = chains[i].n_walkers;
+    offset += chains[i].n_walkers;
+    max_walkers = std::max(max_walkers, chains[i].n_walkers);
+  }
+  // the trials' scoring plan first (it validates the spectrograms and waits
+  // for its own table copies), then the chain table
+  std::vector<emri_problem> pbs = trial_problems(chains, n_chains, ws, L);
+  SearchPlanData pd{};
+  if ((st = score_batched_plan(pbs.data(), n_chains, K, opts, ws + L.scoring, workspace_bytes - L.scoring,
+                               &pd.scoring, hip_stream)) != EMRI_OK)
+    return st;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if ((st = upload_pinv(chains, n_chains, K, ws, L.pinv_off, stream)) != EMRI_OK) return st;
+  hipError_t err = hipMemcpyAsync(ws + L.chains, desc.data(), sizeof(ChainDesc) * desc.size(),
+                                  hipMemcpyHostToDevice, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);     // desc is a host vector
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "search plan copy: %s", hipGetErrorString(err));
+  pd.magic = kSearchMagic;
+  pd.n_chains = n_chains;
+  pd.K = K;
+  pd.max_walkers = max_walkers;
+  pd.chains = reinterpret_cast<const ChainDesc *>(ws + L.chains);
+  std::memset(plan, 0, sizeof *plan);
+  std::memcpy(plan, &pd, sizeof pd);
+  return EMRI_OK;
+}
+
+static int plan_data(const emri_search_plan *plan, SearchPlanData *pd) {
+  if (!plan) return fail(EMRI_EINVAL, "plan is NULL");
+  std::memcpy(pd, plan, sizeof *pd);
+  if (pd->magic != kSearchMagic) return fail(EMRI_EINVAL, "plan was not made by search_plan");
+  return EMRI_OK;
+}
+
+extern "C" int search_generation(const emri_search_plan *plan, const int32_t *r1, const int32_t *r2, const double *F,
+                                 int32_t *accepted, void *hip_stream) {
+  clear_error();
+  SearchPlanData pd;
+  int st = plan_data(plan, &pd);
+  if (st) return st;
+  if (!r1 || !r2 || !F) return fail(EMRI_EINVAL, "r1, r2 and F are required");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const dim3 grid = walker_grid(pd.max_walkers, pd.n_chains);
+  hipError_t err = launch_trials(pd.K, grid, stream, pd.chains, r1, r2, F, AllK{});
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "trial launch: %s", hipGetErrorString(err));
+  if ((st = score_batched_run(&pd.scoring, hip_stream)) != EMRI_OK) return st;
+  hipLaunchKernelGGL(de_select_kernel, grid, dim3(kSearchThreads), 0, stream, pd.chains, pd.K, accepted);
+  err = hipGetLastError();
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "select launch: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}
+
+extern "C" int search_best(const emri_search_plan *plan, const double *noise_mean, const double *noise_std,
+                           float *best_stat, int32_t *best_idx, double *best_norm, void *hip_stream) {
+  clear_error();
+  SearchPlanData pd;
+  int st = plan_data(plan, &pd);
+  if (st) return st;
+  if (!best_stat || !best_idx) return fail(EMRI_EINVAL, "best_stat and best_idx are required");
+  if (best_norm && (!noise_mean || !noise_std)) return fail(EMRI_EINVAL, "best_norm needs noise_mean and noise_std");
+  hipLaunchKernelGGL(search_best_kernel, dim3(pd.n_chains), dim3(kSearchThreads), 0,
+                     reinterpret_cast<hipStream_t>(hip_stream), pd.chains, noise_mean, noise_std, best_stat, best_idx,
+                     best_norm);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "best launch: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}
+
+extern "C" int search_noise_moments(const float *best, int32_t n_real, int32_t n_chains, double *mean, double *sd,
+                                    void *hip_stream) {
+  clear_error();
+  if (!best || !mean || !sd) return fail(EMRI_EINVAL, "NULL argument");
+  if (n_real < 2 || n_chains < 1) return fail(EMRI_EINVAL, "need n_real >= 2 and n_chains >= 1");
+  hipLaunchKernelGGL(noise_moments_kernel, dim3((unsigned)((n_chains + kSearchThreads - 1) / kSearchThreads)),
+                     dim3(kSearchThreads), 0, reinterpret_cast<hipStream_t>(hip_stream), best, n_real, n_chains, mean,
+                     sd);
+  const hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "moments launch: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}
+
+namespace {
+
+// Per chain, at 256-byte strides: candidates (n_draw x K FP32), their
+// statistics, the top-n_walkers values and indices; then the chain table and
+// the candidates' scoring workspace.
+struct SeedLayout {
+  int64_t cand_stride, stat_stride, top_stride;     // elements per chain
+  size_t cand, stat, top_val, top_idx, table, scoring, total;
+  std::vector<size_t> pinv_off;
+};
+
+SeedLayout seed_layout(const emri_chain *chains, int n_chains, int n_draw, int max_walkers, int K,
+                       size_t scoring_bytes) {
+  SeedLayout L;
+  L.cand_stride = (int64_t)round_up((size_t)n_draw * K, 64);
+  L.stat_stride = (int64_t)round_up((size_t)n_draw, 64);
+  L.top_stride = (int64_t)round_up((size_t)max_walkers, 64);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += round_up(bytes > 0 ? bytes : 1, 256);
+    return at;
+  };
+  L.cand = take(sizeof(float) * (size_t)n_chains * L.cand_stride);
+  L.stat = take(sizeof(float) * (size_t)n_chains * L.stat_stride);
+  L.top_val = take(sizeof(float) * (size_t)n_chains * L.top_stride);
+  L.top_idx = take(sizeof(int64_t) * (size_t)n_chains * L.top_stride);
+  L.table = take(sizeof(ChainDesc) * (size_t)n_chains);
+  for (int i = 0; i < n_chains; ++i) L.pinv_off.push_back(take(sizeof(double) * (size_t)chains[i].power.n_seg * K));
+  L.scoring = take(scoring_bytes);
+  L.total = off;
+  return L;
+}
+
+// Candidate problems of the seeding: chain i's n_draw candidates, top n_walkers.
+std::vector<emri_problem> seed_problems(const emri_chain *chains, int n, int n_draw, char *ws, const SeedLayout &L) {
+  std::vector<emri_problem> pbs((size_t)n);
+  // sizing calls pass no workspace: any aligned non-null address stands in
+  char *base = ws ? ws : reinterpret_cast<char *>(256);
+  for (int i = 0; i < n; ++i) {
+    emri_problem &p = pbs[i];
+    std::memset(&p, 0, sizeof p);
+    p.power = chains[i].power;
+    p.f0 = chains[i].f0;
+    p.U = chains[i].U;
+    p.coeffs = reinterpret_cast<const float *>(base + L.cand + sizeof(float) * (size_t)i * L.cand_stride);
+    p.n_tmpl = n_draw;
+    p.top_k = chains[i].n_walkers;
+    p.k_min = chains[i].k_min;
+    p.k_max = chains[i].k_max;
+    p.stat = reinterpret_cast<float *>(base + L.stat + sizeof(float) * (size_t)i * L.stat_stride);
+    p.topk_val = reinterpret_cast<float *>(base + L.top_val + sizeof(float) * (size_t)i * L.top_stride);
+    p.topk_idx = reinterpret_cast<int64_t *>(base + L.top_idx + sizeof(int64_t) * (size_t)i * L.top_stride);
+  }
+  return pbs;
+}
+
+int seed_sizes(const emri_chain *chains, int32_t n_chains, int32_t K, int32_t n_draw, int *max_walkers,
+               size_t *scoring) {
+  int st = validate_chains(chains, n_chains, K);
+  if (st) return st;
+  if (n_draw < 1 || n_draw > (1 << 28)) return fail(EMRI_EINVAL, "n_draw %d out of range", n_draw);
+  *max_walkers = 0;
+  for (int i = 0; i < n_chains; ++i) {
+    if (chains[i].n_walkers > n_draw)
+      return fail(EMRI_EINVAL, "chain %d keeps %d walkers of only %d candidates", i, chains[i].n_walkers, n_draw);
+    if (chains[i].n_walkers > EMRI_MAX_TOPK)
+      return fail(EMRI_EUNSUPPORTED, "chain %d: seeding keeps at most %d walkers", i, EMRI_MAX_TOPK);
+    *max_walkers = std::max(*max_walkers, chains[i].n_walkers);
+  }
+  const SeedLayout L0 = seed_layout(chains, n_chains, n_draw, *max_walkers, K, 0);
+  std::vector<emri_problem> pbs = seed_problems(chains, n_chains, n_draw, nullptr, L0);
+  return score_batched_workspace_size(pbs.data(), n_chains, K, scoring);
+}
+
+}  // namespace
+
+extern "C" int search_seed_workspace_size(const emri_chain *chains, int32_t n_chains, int32_t K, int32_t n_draw,
+                                          size_t *bytes) {
+  clear_error();
+  if (!bytes) return fail(EMRI_EINVAL, "bytes is NULL");
+  int mw = 0;
+  size_t sb = 0;
+  const int st = seed_sizes(chains, n_chains, K, n_draw, &mw, &sb);
+  if (st) return st;
+  *bytes = seed_layout(chains, n_chains, n_draw, mw, K, sb).total;
+  return EMRI_OK;
+}
+
+extern "C" int search_seed(const emri_chain *chains, int32_t n_chains, int32_t K, const float *draws,
+                           const double *f_init, int32_t n_draw, const batch_opts *opts, void *workspace,
+                           size_t workspace_bytes, void *hip_stream) {
+  clear_error();
+  if (!workspace || !draws || !f_init) return fail(EMRI_EINVAL, "NULL argument");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
+  if (!aligned16(draws) || !aligned16(f_init)) return fail(EMRI_EINVAL, "device pointers must be 16-byte aligned");
+  int mw = 0;
+  size_t sb = 0;
+  int st = seed_sizes(chains, n_chains, K, n_draw, &mw, &sb);
+  if (st) return st;
+  const SeedLayout L = seed_layout(chains, n_chains, n_draw, mw, K, sb);
+  if (workspace_bytes < L.total)
+    return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
+  char *ws = reinterpret_cast<char *>(workspace);
+  std::vector<ChainDesc> desc((size_t)n_chains);
+  for (int i = 0; i < n_chains; ++i) {
+    std::memset(&desc[i], 0, sizeof desc[i]);
+    desc[i].f0 = chains[i].f0;
+    desc[i].U = chains[i].U;
+    desc[i].pinvt = reinterpret_cast<const double *>(ws + L.pinv_off[i]);
+    desc[i].coeffs = chains[i].coeffs;
+    desc[i].stat = chains[i].stat;
+    desc[i].n_seg = chains[i].power.n_seg;
+    desc[i].n_walkers = chains[i].n_walkers;
+  }
+  std::vector<emri_problem> pbs = seed_problems(chains, n_chains, n_draw, ws, L);
+  emri_batch_plan scoring;
+  if ((st = score_batched_plan(pbs.data(), n_chains, K, opts, ws + L.scoring, workspace_bytes - L.scoring, &scoring,
+                               hip_stream)) != EMRI_OK)
+    return st;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  ChainDesc *d_desc = reinterpret_cast<ChainDesc *>(ws + L.table);
+  if ((st = upload_pinv(chains, n_chains, K, ws, L.pinv_off, stream)) != EMRI_OK) return st;
+  hipError_t err = hipMemcpyAsync(d_desc, desc.data(), sizeof(ChainDesc) * desc.size(), hipMemcpyHostToDevice, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);      // desc is a host vector
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "seed table copy: %s", hipGetErrorString(err));
+  float *cand = reinterpret_cast<float *>(ws + L.cand);
+  err = launch_seed_move(K, walker_grid(n_draw, n_chains), stream, d_desc, draws, f_init, n_draw, cand, L.cand_stride,
+                         AllK{});
+  if (err != hipSuccess) return fail(EMRI_EDEVICE, "seed launch: %s", hipGetErrorString(err));
+  if ((st = score_batched_run(&scoring, hip_stream)) != EMRI_OK) return st;
+  hipLaunchKernelGGL(seed_gather_kernel, walker_grid(mw, n_chains), dim3(kSearchThreads), 0, stream, d_desc, K, cand,
+                     L.cand_stride, reinterpret_cast<const float *>(ws + L.top_val),
+                     reinterpret_cast<const int64_t *>(ws + L.top_idx), L.top_stride);
+  if ((err = hipGetLastError()) != hipSuccess) return fail(EMRI_EDEVICE, "seed gather: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}

@@ -315,3 +315,25 @@ def search_generation_draws(cfg: int, chain: int, gen: int, n: int, f_lo: float 
     r2 = r2 + (r2 >= b)
     F = g.uniform(f_lo, f_hi, n)
     return r1.astype(np.int32), r2.astype(np.int32), F
+
+
+def device_generation_draws(cfg: int, n_gen: int, walkers: list, device="cuda", f_lo: float = 0.3, f_hi: float = 1.5):
+    """Partners and weights of n_gen generations for chains of the given walker
+    counts (concatenated), drawn on the GPU (torch's Philox generator seeded
+    with cfg); the same law as ``search_generation_draws``, for benchmark runs.
+    Returns int32 r1, r2 and float64 F tensors of shape (n_gen, sum(walkers))."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(2_000_003 * int(cfg) + 17)
+    n = torch.cat([torch.full((w,), int(w), dtype=torch.int64, device=device) for w in walkers])
+    i = torch.cat([torch.arange(w, dtype=torch.int64, device=device) for w in walkers])
+    tot = int(n.numel())
+    u1 = torch.rand((n_gen, tot), dtype=torch.float64, device=device, generator=gen)
+    u2 = torch.rand((n_gen, tot), dtype=torch.float64, device=device, generator=gen)
+    r1 = (i + 1 + torch.floor(u1 * (n - 1)).to(torch.int64)) % n
+    u = torch.floor(u2 * (n - 2)).to(torch.int64)
+    a, b = torch.minimum(i, r1), torch.maximum(i, r1)
+    r2 = u + (u >= a).to(torch.int64)
+    r2 = r2 + (r2 >= b).to(torch.int64)
+    F = f_lo + (f_hi - f_lo) * torch.rand((n_gen, tot), dtype=torch.float64, device=device, generator=gen)
+    return r1.to(torch.int32), r2.to(torch.int32), F

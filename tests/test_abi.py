@@ -240,3 +240,39 @@ def test_noalloc_limit_and_rejections():
     assert call(33, FAKE, K=33) == -1
     assert call(-1, FAKE) == -1
     assert call(10, FAKE + 4) == -1
+
+
+def _chain(n_walkers=16, n_seg=4, f0=FAKE, box=FAKE, coeffs=FAKE, reserved=0):
+    from paper_2510_20891_amd import _Chain
+    c = _Chain()
+    c.power = _power(n_seg=n_seg)
+    c.f0, c.U, c.box_lo, c.box_hi, c.coeffs, c.stat = f0, FAKE, box, box, coeffs, FAKE
+    c.n_walkers, c.k_min, c.k_max, c.reserved = n_walkers, 0, -1, reserved
+    return c
+
+
+@pytest.mark.parametrize("kw,K,status", [
+    (dict(n_walkers=2), 8, -1), (dict(), 0, -1), (dict(), 33, -1), (dict(f0=None), 8, -1),
+    (dict(box=None), 8, -1), (dict(coeffs=FAKE + 4), 8, -1), (dict(reserved=1), 8, -1), (dict(n_seg=0), 8, -1),
+])
+def test_search_rejects(kw, K, status):
+    """The search calls validate their chains before any HIP call."""
+    lib = emri.load()
+    arr = (emri._Chain * 1)(_chain(**kw))
+    nb = ctypes.c_size_t(0)
+    assert lib.search_workspace_size(arr, 1, K, ctypes.byref(nb)) == status
+    assert lib.search_seed_workspace_size(arr, 1, K, 64, ctypes.byref(nb)) == status
+    assert lib.emri_last_error()
+
+
+def test_search_sizes_and_plan_arguments():
+    lib = emri.load()
+    arr = (emri._Chain * 2)(_chain(), _chain(n_walkers=40, n_seg=9))
+    nb = ctypes.c_size_t(0)
+    assert lib.search_workspace_size(arr, 2, 8, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.search_seed_workspace_size(arr, 2, 8, 64, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.search_seed_workspace_size(arr, 2, 8, 20, ctypes.byref(nb)) == -1     # 40 walkers of 20 draws
+    plan = emri._SearchPlan()
+    assert lib.search_generation(ctypes.byref(plan), FAKE, FAKE, FAKE, None, None) == -1   # not a plan
+    assert lib.search_plan(arr, 2, 8, None, FAKE + 16, 1 << 20, ctypes.byref(plan), None) == -1   # alignment
+    assert lib.search_plan(arr, 2, 8, None, FAKE, 64, ctypes.byref(plan), None) == -3          # too small
