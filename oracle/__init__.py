@@ -16,7 +16,10 @@ Each function is the plain definition of one step, written from the paper:
                       limit, summed over segments, plus the top-k selection of
                       Sec. II D;
 * ``search``       -- the population search of Sec. II D: seeding and the
-                      track-space differential-evolution step of Eq. (11).
+                      track-space differential-evolution step of Eq. (11),
+                      the shifted basis and noise normalisation of the
+                      progressive-duration search;
+* ``harmonics``    -- the multi-harmonic statistic proposed in Sec. IV.
 
 Every function is pinned by the CPU tests against closed forms, brute force on
 tiny inputs and distributional laws (see the test modules); none is marked
@@ -26,11 +29,11 @@ from .sft import build_sfts, hann_periodic, sft_bin_frequencies
 from .basis import build_basis, BOX_Q_LO, BOX_Q_HI
 from .score import (score_tracks, track_positions, chosen_bins, near_tie_mask,
                     topk_order, score_tracks_exact, NEAR_TIE_BAND)
-from . import search
+from . import search, harmonics
 
 __all__ = [
     "build_sfts", "hann_periodic", "sft_bin_frequencies",
     "build_basis", "BOX_Q_LO", "BOX_Q_HI",
     "score_tracks", "track_positions", "chosen_bins", "near_tie_mask", "topk_order",
-    "score_tracks_exact", "NEAR_TIE_BAND", "search",
+    "score_tracks_exact", "NEAR_TIE_BAND", "search", "harmonics",
 ]

@@ -116,6 +116,14 @@ def test_search_progressive_pieces():
     pins_search.check_best_walker(osr.best_walker)
 
 
+def test_harmonics_pins():
+    import oracle.harmonics as ohm
+    from tests import pins_harmonics
+    pins_harmonics.check_harmonics_exact(ohm.score_harmonics)
+    pins_harmonics.check_harmonics_constant_track(ohm.score_harmonics)
+    pins_harmonics.check_harmonics_additive(ohm.score_harmonics)
+
+
 def test_oracle_is_isolated():
     """The oracle imports nothing from the HIP library package."""
     import ast, pathlib

@@ -344,3 +344,32 @@ def _best_last_tie(stat):
 ])
 def test_progressive_mutant_caught(check, fn):
     assert _caught([check], fn), fn.__name__
+
+
+# ---------------------------------------------------------------- harmonics (Sec. IV)
+import oracle.harmonics as ohm
+from tests import pins_harmonics
+
+HARMONIC_PINS = [pins_harmonics.check_harmonics_exact, pins_harmonics.check_harmonics_constant_track,
+                 pins_harmonics.check_harmonics_additive]
+
+
+def _hpos_round_first(x, ratios):
+    r = np.asarray(ratios, dtype=np.float64)
+    return r[:, None, None] * np.rint(np.asarray(x, dtype=np.float64))[None, :, :]
+
+
+def _hpos_inverse(x, ratios):
+    r = np.asarray(ratios, dtype=np.float64)
+    return np.asarray(x, dtype=np.float64)[None, :, :] / r[:, None, None]
+
+
+def _hpos_drop_first(x, ratios):
+    r = np.asarray(ratios, dtype=np.float64)[1:]
+    return r[:, None, None] * np.asarray(x, dtype=np.float64)[None, :, :]
+
+
+@pytest.mark.parametrize("fn", [_hpos_round_first, _hpos_inverse, _hpos_drop_first])
+def test_harmonic_mutant_caught(fn, monkeypatch):
+    monkeypatch.setattr(ohm, "harmonic_positions", fn)
+    assert _caught(HARMONIC_PINS, ohm.score_harmonics), fn.__name__
