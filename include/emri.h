@@ -195,6 +195,27 @@ int score_tracks_noalloc(const emri_power *power, const double *f0, const double
 size_t score_tracks_noalloc_limit(void);
 
 /*
+ * score_tracks_harmonics -- the multi-harmonic statistic (Sec. IV proposes
+ * adding harmonics at a cost proportional to their number).  Harmonic h
+ * follows the searched track scaled by the fixed frequency ratio ratios[h]
+ * (host FP64[n_harm], finite, in (0, 1024]; e.g. 1, 1/2, 3/2 for the m = 2,
+ * 1, 3 harmonics of a circular orbit), and every harmonic's nearest-bin power
+ * is summed:
+ *     S[j] = sum_alpha sum_h P[alpha, rint(ratios[h] x[j, alpha])]
+ * over bins inside [k_min, k_max], with x as in score_tracks (FP64) and the
+ * scaled position rounded half to even as one fused operation (bins agree
+ * with rint of the FP64 product except within ~1e-12 bin of a half-integer).
+ * 1 <= n_harm <= 4 and 1 <= K <= 16 (EMRI_EUNSUPPORTED otherwise); the
+ * precision option must be EMRI_PLAIN.  Other arguments, the workspace
+ * (score_tracks_workspace_size) and the top-k are as in score_tracks; each
+ * harmonic costs one more gather per template and segment.
+ */
+int score_tracks_harmonics(const emri_power *power, const double *f0, const double *U, int32_t K,
+                           const float *coeffs, int64_t n_tmpl, int32_t n_harm, const double *ratios,
+                           int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx,
+                           const score_opts *opts, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
  * Batched form: many scoring problems in one persistent launch.
  *
  * A problem is one batch of coefficient vectors scored against one

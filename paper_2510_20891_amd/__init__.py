@@ -83,6 +83,9 @@ SIGNATURES = {
     "score_tracks_noalloc": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp, _vp,
                                             _vp, _vp, ctypes.POINTER(_Opts), _vp]),
     "score_tracks_noalloc_limit": (_sz, []),
+    "score_tracks_harmonics": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32,
+                                              ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp, _vp,
+                                              ctypes.POINTER(_Opts), _vp, _sz, _vp]),
     "score_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_sz)]),
     "score_batched_tile_options": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "score_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp,
@@ -343,6 +346,42 @@ def score_tracks_noalloc(spec: Spectrogram, f0, U, coeffs, top_k: int, stat, top
         ctypes.byref(opts), _stream(stream)))
 
 
+def score_tracks_harmonics(spec: Spectrogram, f0, U, coeffs, ratios, top_k: int, *, k_min: int = 0,
+                           k_max: int = -1, want_stat: bool = True, out: dict | None = None,
+                           workspace: Workspace | None = None, stream=None) -> dict:
+    """Multi-harmonic statistic: harmonic h follows the track scaled by ratios[h]
+    (1 to 4 harmonics, K from 1 to 16); returns ``stat``, ``topk_val``, ``topk_idx``."""
+    import torch
+    _require_cuda(f0, torch.float64, "f0")
+    _require_cuda(U, torch.float64, "U")
+    _require_cuda(coeffs, torch.float32, "coeffs")
+    K = int(U.shape[1]) if U.dim() == 2 else 0
+    n_tmpl = int(coeffs.shape[0])
+    if coeffs.dim() != 2 or coeffs.shape[1] != K:
+        raise ValueError("coeffs must be (n_tmpl, K)")
+    r = [float(v) for v in ratios]
+    rr = (ctypes.c_double * max(1, len(r)))(*r)
+    dev = coeffs.device
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    out = {} if out is None else out
+    res = {}
+    with torch.cuda.stream(s):
+        if want_stat:
+            res["stat"] = out.get("stat") if out.get("stat") is not None else torch.empty(n_tmpl, dtype=torch.float32, device=dev)
+        res["topk_val"] = out.get("topk_val") if out.get("topk_val") is not None else torch.empty(top_k, dtype=torch.float32, device=dev)
+        res["topk_idx"] = out.get("topk_idx") if out.get("topk_idx") is not None else torch.empty(top_k, dtype=torch.int64, device=dev)
+    nbytes = score_tracks_workspace_size(spec, K, n_tmpl, top_k, not want_stat)
+    ws = workspace if workspace is not None else default_workspace(dev, s)
+    ws_ptr, ws_len = ws.get(nbytes, dev, s)
+    opts = _Opts(int(k_min), int(k_max), PLAIN)
+    pw = spec._struct()
+    _check("score_tracks_harmonics", load().score_tracks_harmonics(
+        ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, len(r), rr,
+        int(top_k), _ptr(res.get("stat")), _ptr(res["topk_val"]) if top_k else None,
+        _ptr(res["topk_idx"]) if top_k else None, ctypes.byref(opts), ws_ptr, ws_len, int(s.cuda_stream)))
+    return res
+
+
 def score_tracks_noalloc_limit() -> int:
     return int(load().score_tracks_noalloc_limit())
 
@@ -560,5 +599,5 @@ def search_noise_moments(best, stream=None):
     return mean, sd
 
 
-__all__ = ["Chain", "SearchPlan", "search_seed", "search_noise_moments", "Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+__all__ = ["score_tracks_harmonics", "Chain", "SearchPlan", "search_seed", "search_noise_moments", "Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
            "Spectrogram", "spectrogram_from_power", "Workspace", "default_workspace", "EmriError", "F32", "F16", "LIB_PATH"]

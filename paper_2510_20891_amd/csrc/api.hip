@@ -108,7 +108,7 @@ int scratch_address(void **out) {
 int score_tracks_impl(const emri_power *power, const double *f0, const double *U, int32_t K, const float *coeffs,
                       int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx, int32_t *bins,
                       int64_t *n_near_tie, const score_opts *opts, void *workspace, size_t workspace_bytes,
-                      void *hip_stream, bool static_scratch);
+                      void *hip_stream, bool static_scratch, int n_harm = 0, const double *ratios = nullptr);
 
 }  // namespace
 
@@ -132,12 +132,23 @@ extern "C" int score_tracks_noalloc(const emri_power *power, const double *f0, c
 
 extern "C" size_t score_tracks_noalloc_limit(void) { return kNoallocScratchBytes; }
 
+extern "C" int score_tracks_harmonics(const emri_power *power, const double *f0, const double *U, int32_t K,
+                                      const float *coeffs, int64_t n_tmpl, int32_t n_harm, const double *ratios,
+                                      int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx,
+                                      const score_opts *opts, void *workspace, size_t workspace_bytes,
+                                      void *hip_stream) {
+  clear_error();
+  if (n_harm < 1) return fail(EMRI_EINVAL, "n_harm must be >= 1");
+  return score_tracks_impl(power, f0, U, K, coeffs, n_tmpl, top_k, stat, topk_val, topk_idx, nullptr, nullptr, opts,
+                           workspace, workspace_bytes, hip_stream, false, n_harm, ratios);
+}
+
 namespace {
 
 int score_tracks_impl(const emri_power *power, const double *f0, const double *U, int32_t K, const float *coeffs,
                       int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx, int32_t *bins,
                       int64_t *n_near_tie, const score_opts *opts, void *workspace, size_t workspace_bytes,
-                      void *hip_stream, bool static_scratch) {
+                      void *hip_stream, bool static_scratch, int n_harm, const double *ratios) {
   int st = check_sizes(power, K, n_tmpl, top_k);
   if (st) return st;
   int k_min = 0, k_max = power->n_bins - 1, precision = EMRI_PLAIN;
@@ -155,6 +166,18 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     return fail(EMRI_EUNSUPPORTED, "the mixed-precision form is built for 1 <= K <= %d, not %d", MIXED_MAX_K, K);
   if (mixed && (bins || n_near_tie))
     return fail(EMRI_EUNSUPPORTED, "bins and n_near_tie come from the plain validation kernel only");
+  const bool harm = n_harm > 0;
+  if (harm) {
+    if (!ratios) return fail(EMRI_EINVAL, "ratios is NULL");
+    if (n_harm > HARMONICS_MAX_H) return fail(EMRI_EUNSUPPORTED, "at most %d harmonics, not %d", HARMONICS_MAX_H, n_harm);
+    for (int h = 0; h < n_harm; ++h)
+      if (!std::isfinite(ratios[h]) || !(ratios[h] > 0.0) || ratios[h] > 1024.0)
+        return fail(EMRI_EINVAL, "harmonic ratio %d must be finite and in (0, 1024]", h);
+    if (K < 1 || K > HARMONICS_MAX_K)
+      return fail(EMRI_EUNSUPPORTED, "the multi-harmonic form is built for 1 <= K <= %d, not %d", HARMONICS_MAX_K, K);
+    if (mixed) return fail(EMRI_EUNSUPPORTED, "the multi-harmonic form evaluates positions in FP64 only");
+    if (bins || n_near_tie) return fail(EMRI_EUNSUPPORTED, "bins and n_near_tie are single-harmonic outputs");
+  }
   if (k_min < 0 || k_max > power->n_bins - 1 || k_min > k_max)
     return fail(EMRI_EINVAL, "bin range [%d, %d] not inside [0, %d]", k_min, k_max, power->n_bins - 1);
   if (power->n_seg > 0 && !power->data) return fail(EMRI_EINVAL, "power->data is NULL");
@@ -248,7 +271,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     }
     // a plain launch with a top-k also runs the top-k's first key pass
     size_t lds = sg.lds;
-    if (top_k > 0 && !mixed && !validate && power->n_seg > 0) {
+    if (top_k > 0 && !mixed && !harm && !validate && power->n_seg > 0) {
       p.topk = reinterpret_cast<TopkState *>(ws + L.topk_off);
       p.topk_kk = (uint32_t)(n_tmpl < top_k ? n_tmpl : top_k);
       lds = std::max(lds, (size_t)TOPK_HIST * sizeof(uint32_t));
@@ -256,7 +279,10 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     const int64_t units = (n_tmpl + SCORE_THREADS - 1) / SCORE_THREADS;
     const int grid = (int)(units < cus ? units : cus);
     p.per_block = (n_tmpl + grid - 1) / grid;
-    if (mixed && power->n_seg > 0) {
+    if (harm && power->n_seg > 0) {
+      p.topk = nullptr;
+      err = launch_score_harmonics(p, K, power->dtype, n_harm, ratios, grid, sg.lds, stream);
+    } else if (mixed && power->n_seg > 0) {
       err = launch_score_mixed(p, K, power->dtype, grid, mtab_lds + sg.lds, stream);
     } else if (power->n_seg == 0) {
       // no segment contributes: every statistic is zero; reuse the validation
@@ -268,7 +294,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score launch: %s", hipGetErrorString(err));
   }
   if (top_k > 0) {
-    const int first_pass = (n_tmpl > 0 && !mixed && !validate && power->n_seg > 0) ? 1 : 0;
+    const int first_pass = (n_tmpl > 0 && !mixed && !harm && !validate && power->n_seg > 0) ? 1 : 0;
     err = launch_topk(stat_buf, n_tmpl, top_k, topk_val, topk_idx, ws + L.topk_off, cus, stream, first_pass);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "top-k launch: %s", hipGetErrorString(err));
   }

@@ -115,5 +115,10 @@ hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream);
 int mixed_templates_per_lane(int K);
 hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream);
 hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream);
+// multi-harmonic form (harmonics.hip): 1 <= K <= HARMONICS_MAX_K, 1 <= n_harm <= 4
+constexpr int HARMONICS_MAX_K = 16;
+constexpr int HARMONICS_MAX_H = 4;
+hipError_t launch_score_harmonics(const ScoreParams &p, int K, int dtype, int n_harm, const double *ratios, int grid,
+                                  size_t lds, hipStream_t stream);
 
 }  // namespace emri

@@ -276,3 +276,26 @@ def test_search_sizes_and_plan_arguments():
     assert lib.search_generation(ctypes.byref(plan), FAKE, FAKE, FAKE, None, None) == -1   # not a plan
     assert lib.search_plan(arr, 2, 8, None, FAKE + 16, 1 << 20, ctypes.byref(plan), None) == -1   # alignment
     assert lib.search_plan(arr, 2, 8, None, FAKE, 64, ctypes.byref(plan), None) == -3          # too small
+
+
+@pytest.mark.parametrize("n_harm,ratios,K,status", [
+    (0, [1.0], 8, -1), (5, [1.0] * 5, 8, -5), (2, [1.0, float("nan")], 8, -1), (2, [1.0, -0.5], 8, -1),
+    (2, [1.0, 2000.0], 8, -1), (2, [1.0, 0.5], 17, -5), (2, [1.0, 0.5], 0, -5),
+])
+def test_harmonics_rejects(n_harm, ratios, K, status):
+    lib = emri.load()
+    pw = _power()
+    rr = (ctypes.c_double * max(1, len(ratios)))(*ratios)
+    st = lib.score_tracks_harmonics(ctypes.byref(pw), FAKE, FAKE, K, FAKE, 10, n_harm, rr, 4, FAKE, FAKE, FAKE,
+                                    None, FAKE, 1 << 20, None)
+    assert st == status
+    assert lib.emri_last_error()
+
+
+def test_harmonics_rejects_mixed_precision():
+    lib = emri.load()
+    pw = _power()
+    rr = (ctypes.c_double * 2)(1.0, 0.5)
+    opts = _Opts(0, -1, 1)
+    assert lib.score_tracks_harmonics(ctypes.byref(pw), FAKE, FAKE, 8, FAKE, 10, 2, rr, 4, FAKE, FAKE, FAKE,
+                                      ctypes.byref(opts), FAKE, 1 << 20, None) == -5
