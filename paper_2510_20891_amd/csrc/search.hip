@@ -3,22 +3,22 @@
 // at once (a chain is one population against one spectrogram and basis; the
 // progressive-duration search runs one chain per observed duration).
 //
-// One generation is three launches, all reading device tables written by
+// One generation is two launches, both reading device tables written by
 // search_plan, so a generation (or many) can be captured into a HIP graph:
-//   1. de_trials_kernel: per walker (one lane each), the trial track
+//   1. de_trial_score_kernel: per walker (eight lanes each), the trial track
 //      f_trial = f + F (f_r1 - f_r2) is formed segment by segment in FP64
-//      (f = f0 + U c), and projected back onto the basis with its
-//      pseudo-inverse, c_trial = pinv(U) (f_trial - f0), stored as FP32 (a
-//      chain's basis rows are a time-shifted part of the one-year basis, no
-//      longer orthonormal; the plan computes each chain's pseudo-inverse on
-//      the host, FP64 one-sided Jacobi, and keeps it in the workspace);
-//   2. the batched scoring launch over every chain's trials (one persistent
-//      launch, score_batched_run);
-//   3. de_select_kernel: a trial inside the prior box (bounds included) whose
+//      (f = f0 + U c), projected back onto the basis with its pseudo-inverse,
+//      c_trial = pinv(U) (f_trial - f0), rounded to FP32 (a chain's basis
+//      rows are a time-shifted part of the one-year basis, no longer
+//      orthonormal; the plan computes each chain's pseudo-inverse on the
+//      host, FP64 one-sided Jacobi, and keeps it in the workspace), and
+//      scored with power gathered from the spectrogram in place;
+//   2. de_select_kernel: a trial inside the prior box (bounds included) whose
 //      statistic is strictly higher replaces the walker.
 // Walkers whose partner indices are out of range or not distinct keep their
 // current vector (their trial is never accepted).
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include <algorithm>
 #include <cmath>
@@ -35,6 +35,11 @@ using namespace emri;
 namespace {
 
 constexpr uint32_t kSearchMagic = 0x45534348u;   // "ESCH"
+
+template <typename T>
+struct type_tag {
+  using type = T;
+};
 constexpr int kSearchThreads = 256;
 
 // One chain as the kernels see it (device table).
@@ -43,8 +48,13 @@ struct ChainDesc {
   const double *pinvt;             // pinv(U) transposed: n_seg x K (workspace)
   float *coeffs, *stat;            // the walkers (updated in place)
   float *trial, *trial_stat;       // this generation's trials (workspace)
+  const void *power;               // spectrogram rows (FP32 or FP16)
+  double t_sft;
   int64_t offset;                  // first walker of the chain in the concatenated draws
   int32_t n_seg, n_walkers;
+  int32_t pitch;                   // elements between spectrogram rows
+  int32_t k_min, k_max;
+  int32_t pad;
 };
 
 // What search_generation needs, kept in the caller's emri_search_plan.
@@ -53,8 +63,9 @@ struct SearchPlanData {
   int32_t n_chains;
   int32_t K;
   int32_t max_walkers;
+  int32_t max_seg;
+  int32_t dtype;
   const ChainDesc *chains;
-  emri_batch_plan scoring;
 };
 static_assert(sizeof(SearchPlanData) <= sizeof(emri_search_plan), "search plan does not fit");
 
@@ -67,38 +78,51 @@ __device__ __forceinline__ double track_at(const double *f0, const double *Ua, c
   return f;
 }
 
-template <int K>
-__global__ __launch_bounds__(kSearchThreads) void de_trials_kernel(const ChainDesc *__restrict__ chains,
-                                                                   const int32_t *__restrict__ r1,
-                                                                   const int32_t *__restrict__ r2,
-                                                                   const double *__restrict__ F) {
-  const ChainDesc ch = load_uniform(chains + blockIdx.y);
-  const int i = blockIdx.x * kSearchThreads + threadIdx.x;
-  if (i >= ch.n_walkers) return;
-  const int64_t gi = ch.offset + i;
-  const int a = r1[gi], b = r2[gi];
-  const bool valid = a >= 0 && a < ch.n_walkers && b >= 0 && b < ch.n_walkers && a != i && b != i && a != b;
-  double ci[K], ca[K], cb[K], out[K];
+// The chain's basis rows (f0, U and the transposed pseudo-inverse), staged
+// in LDS when they fit (every lane reads every row), else read in place.  In
+// LDS a row of K doubles is padded to an odd number of doubles, so that the
+// eight different rows the eight lanes of a walker read at once fall in
+// different banks.
+struct BasisRows {
+  const double *f0, *U, *P;
+  int stride;                      // doubles between consecutive rows of U and P
+};
+
+__host__ __device__ constexpr int padded_stride(int K) { return (K % 2 == 0) ? K + 1 : K; }
+
+template <bool STAGE, int NT = kSearchThreads>
+__device__ __forceinline__ BasisRows basis_rows(const ChainDesc &ch, int K, double *lds) {
+  if constexpr (!STAGE) {
+    return BasisRows{ch.f0, ch.U, ch.pinvt, K};
+  } else {
+    // f0 | U rows | pinv^T rows, eight loads in flight per lane before their stores
+    const int n = ch.n_seg, nk = n * K, total = n + 2 * nk, ps = padded_stride(K);
+    double *f0s = lds, *Us = lds + n, *Ps = lds + n + (size_t)n * ps;
+    constexpr int D = 8;
+    for (int e0 = threadIdx.x; e0 < total; e0 += D * NT) {
+      double v[D];
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    ci[k] = (double)ch.coeffs[(size_t)i * K + k];
-    ca[k] = valid ? (double)ch.coeffs[(size_t)a * K + k] : ci[k];
-    cb[k] = valid ? (double)ch.coeffs[(size_t)b * K + k] : ci[k];
-    out[k] = 0.0;
+      for (int u = 0; u < D; ++u) {
+        const int e = e0 + u * NT;
+        v[u] = e < n ? ch.f0[e] : (e < n + nk ? ch.U[e - n] : (e < total ? ch.pinvt[e - n - nk] : 0.0));
+      }
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        const int e = e0 + u * NT;
+        if (e < n) {
+          f0s[e] = v[u];
+        } else if (e < n + nk) {
+          const int q = e - n;
+          Us[(q / K) * ps + q % K] = v[u];
+        } else if (e < total) {
+          const int q = e - n - nk;
+          Ps[(q / K) * ps + q % K] = v[u];
+        }
+      }
+    }
+    __syncthreads();
+    return BasisRows{f0s, Us, Ps, ps};
   }
-  const double w = valid ? F[gi] : 0.0;
-  for (int alpha = 0; alpha < ch.n_seg; ++alpha) {
-    const double *Ua = ch.U + (size_t)alpha * K;
-    const double fi = track_at<K>(ch.f0, Ua, ci, alpha);
-    const double fa = track_at<K>(ch.f0, Ua, ca, alpha);
-    const double fb = track_at<K>(ch.f0, Ua, cb, alpha);
-    const double d = __builtin_fma(w, fa - fb, fi) - ch.f0[alpha];     // f_trial - f0
-    const double *Pa = ch.pinvt + (size_t)alpha * K;
-#pragma unroll
-    for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < K; ++k) ch.trial[(size_t)i * K + k] = valid ? (float)out[k] : __builtin_nanf("");
 }
 
 __global__ __launch_bounds__(kSearchThreads) void de_select_kernel(const ChainDesc *__restrict__ chains, int K,
@@ -120,16 +144,129 @@ __global__ __launch_bounds__(kSearchThreads) void de_select_kernel(const ChainDe
   if (accepted) accepted[ch.offset + i] = take ? 1 : 0;
 }
 
+// One generation's trials, formed and scored in one launch (the population
+// is only read; de_select_kernel writes it afterwards).  Eight lanes work on
+// one walker: lane s takes segments s, s + 8, s + 16, ...; the projection's
+// partial sums and the statistic's partial sums are combined across the
+// lanes with shuffles in a fixed order.  The trial's coefficients are rounded
+// to FP32 (the walkers' representation) before its positions are evaluated
+// in FP64 as in score_tracks, x = f0 T + sum_k c_k (U T)[alpha, k], rounded to
+// the nearest bin (half to even); the power is gathered from the spectrogram
+// in place (a population of a few hundred walkers reads too few elements of a
+// row to pay for staging rows in LDS), eight gathers in flight per lane.  Each
+// lane sums its segments in FP32 runs of 8 and in FP64 across runs and lanes.
+constexpr int kLanesPerWalker = 8;      // measured: 16 lanes and 512 threads 33 us, 8 and 256 27 us
+constexpr int kTrialThreads = 256;
+constexpr int kWalkersPerBlock = kTrialThreads / kLanesPerWalker;
+
+template <typename PT>
+__device__ __forceinline__ float power_at(const void *p, size_t at);
+template <>
+__device__ __forceinline__ float power_at<float>(const void *p, size_t at) {
+  return reinterpret_cast<const float *>(p)[at];
+}
+template <>
+__device__ __forceinline__ float power_at<__half>(const void *p, size_t at) {
+  return (float)__builtin_bit_cast(_Float16, reinterpret_cast<const unsigned short *>(p)[at]);
+}
+
+template <int K, bool STAGE, typename PT>
+__global__ __launch_bounds__(kTrialThreads) void de_trial_score_kernel(const ChainDesc *__restrict__ chains,
+                                                                        const int32_t *__restrict__ r1,
+                                                                        const int32_t *__restrict__ r2,
+                                                                        const double *__restrict__ F) {
+  extern __shared__ double stage_rows[];
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  if ((int)(blockIdx.x * kWalkersPerBlock) >= ch.n_walkers) return;    // whole workgroup idle
+  const BasisRows B = basis_rows<STAGE, kTrialThreads>(ch, K, stage_rows);
+  const int sub = (int)(threadIdx.x & (kLanesPerWalker - 1));
+  const int i_raw = blockIdx.x * kWalkersPerBlock + (int)(threadIdx.x / kLanesPerWalker);
+  const bool live = i_raw < ch.n_walkers;
+  const int i = live ? i_raw : 0;                  // idle lanes compute walker 0 and store nothing
+  const int64_t gi = ch.offset + i;
+  const int a = r1[gi], b = r2[gi];
+  const bool valid = a >= 0 && a < ch.n_walkers && b >= 0 && b < ch.n_walkers && a != i && b != i && a != b;
+  double ci[K], ca[K], cb[K], out[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    ci[k] = (double)ch.coeffs[(size_t)i * K + k];
+    ca[k] = valid ? (double)ch.coeffs[(size_t)a * K + k] : ci[k];
+    cb[k] = valid ? (double)ch.coeffs[(size_t)b * K + k] : ci[k];
+    out[k] = 0.0;
+  }
+  const double w = valid ? F[gi] : 0.0;
+  for (int alpha = sub; alpha < ch.n_seg; alpha += kLanesPerWalker) {
+    const double *Ua = B.U + (size_t)alpha * B.stride;
+    const double fi = track_at<K>(B.f0, Ua, ci, alpha);
+    const double fa = track_at<K>(B.f0, Ua, ca, alpha);
+    const double fb = track_at<K>(B.f0, Ua, cb, alpha);
+    const double d = __builtin_fma(w, fa - fb, fi) - B.f0[alpha];     // f_trial - f0
+    const double *Pa = B.P + (size_t)alpha * B.stride;
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
+  }
+  float ct[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = out[k];
+#pragma unroll
+    for (int off = kLanesPerWalker / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanesPerWalker);
+    ct[k] = valid ? (float)v : __builtin_nanf("");
+  }
+  // the trial's statistic
+  // eight segments per lane at a time: their bins first, then their eight
+  // gathers in flight together, then one FP32 run summed into FP64
+  const double T = ch.t_sft;
+  double sum = 0.0;
+  constexpr int RUN = 8;
+  for (int alpha0 = sub; alpha0 < ch.n_seg; alpha0 += RUN * kLanesPerWalker) {
+    size_t at[RUN];
+    bool in[RUN];
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) {
+      const int alpha = alpha0 + u * kLanesPerWalker;
+      const int ar = alpha < ch.n_seg ? alpha : sub;
+      const double *Ua = B.U + (size_t)ar * B.stride;
+      double x = B.f0[ar] * T;
+#pragma unroll
+      for (int k = 0; k < K; ++k) x = __builtin_fma((double)ct[k], Ua[k] * T, x);
+      const bool finite = __builtin_fabs(x) < 67108864.0;                // 2^26 bins; NaN fails
+      const int bin = finite ? (int)__builtin_rint(x) : -1;
+      in[u] = alpha < ch.n_seg && finite && bin >= ch.k_min && bin <= ch.k_max;
+      at[u] = (size_t)ar * ch.pitch + (in[u] ? bin : ch.k_min);
+    }
+    float v[RUN];
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) v[u] = power_at<PT>(ch.power, at[u]);
+    float acc = 0.0f;
+#pragma unroll
+    for (int u = 0; u < RUN; ++u) acc += in[u] ? v[u] : 0.0f;
+    sum += (double)acc;
+  }
+#pragma unroll
+  for (int off = kLanesPerWalker / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kLanesPerWalker);
+  if (live) {
+    for (int k = sub; k < K; k += kLanesPerWalker) {
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        if (q == k) ch.trial[(size_t)i * K + k] = ct[q];
+    }
+    if (sub == 0) ch.trial_stat[i] = valid ? (float)sum : -__builtin_inff();
+  }
+}
+
 // Seeding: every candidate's track is moved by one constant so that its first
 // segment sits at f_init, then projected back (FP32 result).  Chain c's
 // candidates are draws[c * n_draw + j] (K values each); cand holds them at a
 // stride of cand_stride floats per chain.
-template <int K>
+template <int K, bool STAGE>
 __global__ __launch_bounds__(kSearchThreads) void seed_move_kernel(const ChainDesc *__restrict__ chains,
                                                                    const float *__restrict__ draws,
                                                                    const double *__restrict__ f_init, int n_draw,
                                                                    float *__restrict__ cand, int64_t cand_stride) {
+  extern __shared__ double stage_rows[];
   const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  const BasisRows B = basis_rows<STAGE>(ch, K, stage_rows);
   const int j = blockIdx.x * kSearchThreads + threadIdx.x;
   if (j >= n_draw) return;
   const int64_t gj = (int64_t)blockIdx.y * n_draw + j;
@@ -139,11 +276,11 @@ __global__ __launch_bounds__(kSearchThreads) void seed_move_kernel(const ChainDe
     c[k] = (double)draws[(size_t)gj * K + k];
     out[k] = 0.0;
   }
-  const double shift = f_init[gj] - track_at<K>(ch.f0, ch.U, c, 0);
+  const double shift = f_init[gj] - track_at<K>(B.f0, B.U, c, 0);
   for (int alpha = 0; alpha < ch.n_seg; ++alpha) {
-    const double *Ua = ch.U + (size_t)alpha * K;
-    const double d = (track_at<K>(ch.f0, Ua, c, alpha) + shift) - ch.f0[alpha];
-    const double *Pa = ch.pinvt + (size_t)alpha * K;
+    const double *Ua = B.U + (size_t)alpha * B.stride;
+    const double d = (track_at<K>(B.f0, Ua, c, alpha) + shift) - B.f0[alpha];
+    const double *Pa = B.P + (size_t)alpha * B.stride;
 #pragma unroll
     for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
   }
@@ -236,28 +373,51 @@ __global__ __launch_bounds__(kSearchThreads) void noise_moments_kernel(const flo
   sd[c] = __builtin_sqrt(q / (n_real - 1));
 }
 
+// Bytes of LDS that stage a chain of n_seg rows, or 0 when they do not fit
+// (the kernels then read the rows in place).
+constexpr size_t kStageLimit = 160 * 1024;
+size_t stage_bytes(int max_seg, int K) {
+  const size_t b = sizeof(double) * (size_t)max_seg * (2 * (size_t)padded_stride(K) + 1);
+  return b <= kStageLimit ? b : 0;
+}
+
 template <int... Ks>
-hipError_t launch_trials(int K, dim3 grid, hipStream_t stream, const ChainDesc *chains, const int32_t *r1,
-                         const int32_t *r2, const double *F, std::integer_sequence<int, Ks...>) {
+hipError_t launch_trial_score(int K, int dtype, int max_seg, dim3 grid, hipStream_t stream, const ChainDesc *chains,
+                              const int32_t *r1, const int32_t *r2, const double *F,
+                              std::integer_sequence<int, Ks...>) {
   hipError_t err = hipErrorInvalidValue;
-  auto one = [&](auto kc) {
+  const size_t lds = stage_bytes(max_seg, K);
+  auto one = [&](auto kc, auto pt) {
     constexpr int KK = decltype(kc)::value;
-    hipLaunchKernelGGL(de_trials_kernel<KK>, grid, dim3(kSearchThreads), 0, stream, chains, r1, r2, F);
+    using PT = typename decltype(pt)::type;
+    auto kern = lds ? de_trial_score_kernel<KK, true, PT> : de_trial_score_kernel<KK, false, PT>;
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(kern, grid, dim3(kTrialThreads), lds, stream, chains, r1, r2, F);
     err = hipGetLastError();
   };
-  ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}), true) : false) || ...);
+  if (dtype == EMRI_F32)
+    ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}, type_tag<float>{}), true) : false) || ...);
+  else
+    ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}, type_tag<__half>{}), true) : false) || ...);
   return err;
 }
 
 template <int... Ks>
-hipError_t launch_seed_move(int K, dim3 grid, hipStream_t stream, const ChainDesc *chains, const float *draws,
-                            const double *f_init, int n_draw, float *cand, int64_t cand_stride,
+hipError_t launch_seed_move(int K, int max_seg, dim3 grid, hipStream_t stream, const ChainDesc *chains,
+                            const float *draws, const double *f_init, int n_draw, float *cand, int64_t cand_stride,
                             std::integer_sequence<int, Ks...>) {
   hipError_t err = hipErrorInvalidValue;
+  const size_t lds = stage_bytes(max_seg, K);
   auto one = [&](auto kc) {
     constexpr int KK = decltype(kc)::value;
-    hipLaunchKernelGGL(seed_move_kernel<KK>, grid, dim3(kSearchThreads), 0, stream, chains, draws, f_init, n_draw,
-                       cand, cand_stride);
+    auto kern = lds ? seed_move_kernel<KK, true> : seed_move_kernel<KK, false>;
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(kern, grid, dim3(kSearchThreads), lds, stream, chains, draws, f_init, n_draw, cand,
+                       cand_stride);
     err = hipGetLastError();
   };
   ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}), true) : false) || ...);
@@ -279,11 +439,11 @@ int check_chain(const emri_chain &c, int i) {
 }
 
 struct SearchLayout {
-  size_t chains, trials, scoring, total;
+  size_t chains, trials, total;
   std::vector<size_t> trial_off, tstat_off, pinv_off;
 };
 
-SearchLayout search_layout(const emri_chain *chains, int n, int K, size_t scoring_bytes) {
+SearchLayout search_layout(const emri_chain *chains, int n, int K) {
   SearchLayout L;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -298,30 +458,8 @@ SearchLayout search_layout(const emri_chain *chains, int n, int K, size_t scorin
     L.tstat_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers));
     L.pinv_off.push_back(take(sizeof(double) * (size_t)chains[i].power.n_seg * K));
   }
-  L.scoring = take(scoring_bytes);
   L.total = off;
   return L;
-}
-
-// The scoring problems of the trials: chain i's trial buffer against its spectrogram.
-std::vector<emri_problem> trial_problems(const emri_chain *chains, int n, char *ws, const SearchLayout &L) {
-  std::vector<emri_problem> pbs((size_t)n);
-  // sizing calls pass no workspace: any aligned non-null address stands in
-  char *base = ws ? ws : reinterpret_cast<char *>(256);
-  for (int i = 0; i < n; ++i) {
-    emri_problem &p = pbs[i];
-    std::memset(&p, 0, sizeof p);
-    p.power = chains[i].power;
-    p.f0 = chains[i].f0;
-    p.U = chains[i].U;
-    p.coeffs = reinterpret_cast<const float *>(base + L.trial_off[i]);
-    p.n_tmpl = chains[i].n_walkers;
-    p.top_k = 0;
-    p.k_min = chains[i].k_min;
-    p.k_max = chains[i].k_max;
-    p.stat = reinterpret_cast<float *>(base + L.tstat_off[i]);
-  }
-  return pbs;
 }
 
 int validate_chains(const emri_chain *chains, int32_t n_chains, int32_t K) {
@@ -335,10 +473,20 @@ int validate_chains(const emri_chain *chains, int32_t n_chains, int32_t K) {
   return EMRI_OK;
 }
 
-int scoring_bytes_for(const emri_chain *chains, int n, int K, size_t *bytes) {
-  SearchLayout L0 = search_layout(chains, n, K, 0);
-  std::vector<emri_problem> pbs = trial_problems(chains, n, nullptr, L0);
-  return score_batched_workspace_size(pbs.data(), n, K, bytes);
+// What the trial kernel reads of a chain's spectrogram (the seeding scores
+// through score_batched_plan, which checks the same).
+int check_chain_power(const emri_chain &c, int i, int dtype) {
+  const emri_power &pw = c.power;
+  if (pw.dtype != EMRI_F32 && pw.dtype != EMRI_F16) return fail(EMRI_EINVAL, "chain %d: unknown power dtype", i);
+  if (pw.dtype != dtype) return fail(EMRI_EINVAL, "chain %d: every chain must use the same power dtype", i);
+  if (!pw.data || !aligned16(pw.data)) return fail(EMRI_EINVAL, "chain %d: power data NULL or not 16-byte aligned", i);
+  if (pw.n_bins < 1 || pw.row_pitch < pw.n_bins || (pw.row_pitch % 8) != 0)
+    return fail(EMRI_EINVAL, "chain %d: row_pitch must be a multiple of 8 and >= n_bins", i);
+  if (!std::isfinite(pw.t_sft) || !(pw.t_sft > 0.0)) return fail(EMRI_EINVAL, "chain %d: bad t_sft", i);
+  const int k_max = c.k_max < 0 ? pw.n_bins - 1 : c.k_max;
+  if (c.k_min < 0 || k_max > pw.n_bins - 1 || c.k_min > k_max)
+    return fail(EMRI_EINVAL, "chain %d: bin range outside the row", i);
+  return EMRI_OK;
 }
 
 // Each chain's pseudo-inverse (transposed, n_seg x K) at dst + off[i]: its
@@ -377,9 +525,7 @@ extern "C" int search_workspace_size(const emri_chain *chains, int32_t n_chains,
   if (!bytes) return fail(EMRI_EINVAL, "bytes is NULL");
   int st = validate_chains(chains, n_chains, K);
   if (st) return st;
-  size_t sb = 0;
-  if ((st = scoring_bytes_for(chains, n_chains, K, &sb)) != EMRI_OK) return st;
-  *bytes = search_layout(chains, n_chains, K, sb).total;
+  *bytes = search_layout(chains, n_chains, K).total;
   return EMRI_OK;
 }
 
@@ -390,15 +536,22 @@ extern "C" int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K
   if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return fail(EMRI_EINVAL, "workspace must be 256-byte aligned");
   int st = validate_chains(chains, n_chains, K);
   if (st) return st;
-  size_t sb = 0;
-  if ((st = scoring_bytes_for(chains, n_chains, K, &sb)) != EMRI_OK) return st;
-  const SearchLayout L = search_layout(chains, n_chains, K, sb);
+  if (opts) {
+    for (int i = 0; i < 5; ++i)
+      if (opts->reserved[i] != 0) return fail(EMRI_EINVAL, "batch_opts.reserved must be zero");
+    if (opts->precision != EMRI_PLAIN)
+      return fail(EMRI_EUNSUPPORTED, "generations score with FP64 positions (EMRI_PLAIN) only");
+  }
+  const int dtype = chains[0].power.dtype;
+  for (int i = 0; i < n_chains; ++i)
+    if ((st = check_chain_power(chains[i], i, dtype)) != EMRI_OK) return st;
+  const SearchLayout L = search_layout(chains, n_chains, K);
   if (workspace_bytes < L.total)
     return fail(EMRI_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", workspace_bytes, L.total);
   char *ws = reinterpret_cast<char *>(workspace);
   std::vector<ChainDesc> desc((size_t)n_chains);
   int64_t offset = 0;
-  int max_walkers = 0;
+  int max_walkers = 0, max_seg = 0;
   for (int i = 0; i < n_chains; ++i) {
     ChainDesc &d = desc[i];
     std::memset(&d, 0, sizeof d);
@@ -411,29 +564,31 @@ extern "C" int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K
     d.pinvt = reinterpret_cast<const double *>(ws + L.pinv_off[i]);
     d.trial = reinterpret_cast<float *>(ws + L.trial_off[i]);
     d.trial_stat = reinterpret_cast<float *>(ws + L.tstat_off[i]);
+    d.power = chains[i].power.data;
+    d.t_sft = chains[i].power.t_sft;
     d.offset = offset;
     d.n_seg = chains[i].power.n_seg;
     d.n_walkers = chains[i].n_walkers;
+    d.pitch = chains[i].power.row_pitch;
+    d.k_min = chains[i].k_min;
+    d.k_max = chains[i].k_max < 0 ? chains[i].power.n_bins - 1 : chains[i].k_max;
     offset += chains[i].n_walkers;
     max_walkers = std::max(max_walkers, chains[i].n_walkers);
+    max_seg = std::max(max_seg, chains[i].power.n_seg);
   }
-  // the trials' scoring plan first (it validates the spectrograms and waits
-  // for its own table copies), then the chain table
-  std::vector<emri_problem> pbs = trial_problems(chains, n_chains, ws, L);
-  SearchPlanData pd{};
-  if ((st = score_batched_plan(pbs.data(), n_chains, K, opts, ws + L.scoring, workspace_bytes - L.scoring,
-                               &pd.scoring, hip_stream)) != EMRI_OK)
-    return st;
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   if ((st = upload_pinv(chains, n_chains, K, ws, L.pinv_off, stream)) != EMRI_OK) return st;
   hipError_t err = hipMemcpyAsync(ws + L.chains, desc.data(), sizeof(ChainDesc) * desc.size(),
                                   hipMemcpyHostToDevice, stream);
   if (err == hipSuccess) err = hipStreamSynchronize(stream);     // desc is a host vector
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "search plan copy: %s", hipGetErrorString(err));
+  SearchPlanData pd{};
   pd.magic = kSearchMagic;
   pd.n_chains = n_chains;
   pd.K = K;
   pd.max_walkers = max_walkers;
+  pd.max_seg = max_seg;
+  pd.dtype = dtype;
   pd.chains = reinterpret_cast<const ChainDesc *>(ws + L.chains);
   std::memset(plan, 0, sizeof *plan);
   std::memcpy(plan, &pd, sizeof pd);
@@ -455,11 +610,11 @@ extern "C" int search_generation(const emri_search_plan *plan, const int32_t *r1
   if (st) return st;
   if (!r1 || !r2 || !F) return fail(EMRI_EINVAL, "r1, r2 and F are required");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
-  const dim3 grid = walker_grid(pd.max_walkers, pd.n_chains);
-  hipError_t err = launch_trials(pd.K, grid, stream, pd.chains, r1, r2, F, AllK{});
+  const dim3 sgrid((unsigned)((pd.max_walkers + kWalkersPerBlock - 1) / kWalkersPerBlock), (unsigned)pd.n_chains);
+  hipError_t err = launch_trial_score(pd.K, pd.dtype, pd.max_seg, sgrid, stream, pd.chains, r1, r2, F, AllK{});
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "trial launch: %s", hipGetErrorString(err));
-  if ((st = score_batched_run(&pd.scoring, hip_stream)) != EMRI_OK) return st;
-  hipLaunchKernelGGL(de_select_kernel, grid, dim3(kSearchThreads), 0, stream, pd.chains, pd.K, accepted);
+  hipLaunchKernelGGL(de_select_kernel, walker_grid(pd.max_walkers, pd.n_chains), dim3(kSearchThreads), 0, stream,
+                     pd.chains, pd.K, accepted);
   err = hipGetLastError();
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "select launch: %s", hipGetErrorString(err));
   return EMRI_OK;
@@ -621,8 +776,10 @@ extern "C" int search_seed(const emri_chain *chains, int32_t n_chains, int32_t K
   if (err == hipSuccess) err = hipStreamSynchronize(stream);      // desc is a host vector
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "seed table copy: %s", hipGetErrorString(err));
   float *cand = reinterpret_cast<float *>(ws + L.cand);
-  err = launch_seed_move(K, walker_grid(n_draw, n_chains), stream, d_desc, draws, f_init, n_draw, cand, L.cand_stride,
-                         AllK{});
+  int max_seg = 0;
+  for (int i = 0; i < n_chains; ++i) max_seg = std::max(max_seg, chains[i].power.n_seg);
+  err = launch_seed_move(K, max_seg, walker_grid(n_draw, n_chains), stream, d_desc, draws, f_init, n_draw, cand,
+                         L.cand_stride, AllK{});
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "seed launch: %s", hipGetErrorString(err));
   if ((st = score_batched_run(&scoring, hip_stream)) != EMRI_OK) return st;
   hipLaunchKernelGGL(seed_gather_kernel, walker_grid(mw, n_chains), dim3(kSearchThreads), 0, stream, d_desc, K, cand,
