@@ -122,14 +122,14 @@ def optimal_snr(h: np.ndarray, dt: float, psd_fn) -> float:
 
 
 def injection(n: int, dt: float, f0: float, tau: float, snr: float, psd_fn,
-              phi0: float) -> np.ndarray:
+              phi0: float, t_cut: float | None = None) -> np.ndarray:
     """A cos(Phi(t) + phi0), t = k dt, scaled to the requested SNR.
 
-    The signal is cut (set to zero) from plunge (t >= tau) and wherever its
-    frequency exceeds 0.45/dt, so nothing aliases.
+    The signal is cut (set to zero) from plunge (t >= tau, or t >= t_cut when
+    given) and wherever its frequency exceeds 0.45/dt, so nothing aliases.
     """
     t = np.arange(n) * dt
-    live = t < tau
+    live = t < (tau if t_cut is None else min(tau, t_cut))
     h = np.zeros(n)
     tl = t[live]
     f = chirp_frequency(tl, f0, tau)
@@ -154,6 +154,18 @@ def training_tracks(n_train: int, t_mid: np.ndarray, f0_range, tau_range,
     f0 = g.uniform(f0_range[0], f0_range[1], n_train)
     tau = g.uniform(tau_range[0], tau_range[1], n_train)
     return f0[:, None] * (1.0 - t_mid[None, :] / tau[:, None]) ** (-0.375)
+
+
+def plunge_tracks(n_train: int, t_mid: np.ndarray, t_plunge: float, fp_range, tc_range,
+                  g: np.random.Generator) -> np.ndarray:
+    """[n_train, n_seg] tracks that plunge at t_plunge: the chirp law with
+    coalescence time t_plunge + t_c, cut at the plunge,
+    f(t) = f_p (1 + (t_plunge - t) / t_c)^(-3/8)  (t <= t_plunge),
+    with f_p ~ U[fp_range] (Hz, the frequency at plunge) and t_c ~ logU[tc_range]
+    (seconds).  Stand-ins for trajectory tracks that all end at one plunge time."""
+    fp = g.uniform(fp_range[0], fp_range[1], n_train)
+    tc = np.exp(g.uniform(math.log(tc_range[0]), math.log(tc_range[1]), n_train))
+    return fp[:, None] * (1.0 + (t_plunge - t_mid[None, :]) / tc[:, None]) ** (-0.375)
 
 
 def coefficient_chunk(cfg: int, stream: int, chunk: int, n: int,
@@ -232,6 +244,36 @@ def stream_config1(stream: int = 0, cfg: int = 1, duration_s: float = 3.15e7,
     return dict(cfg=cfg, stream=stream, dt=dt, n_sft=n_sft, x=x, psd_fn=psd_coloured,
                 psd=psd_on_bins(psd_coloured, n_sft, dt), tracks=tracks, K=8,
                 n_tmpl=10_000_000, top_k=256, injection=inj, t_mid=t_mid)
+
+
+def stream_progressive(stream: int = 0, cfg: int = 6, plunge_frac: float = 0.7, snr: float | None = 30.0) -> dict:
+    """The progressive-duration search's stand-in: one year of config-1 noise
+    (3.15e7 s at 10 s, SFTs of 16384 samples, 192 segments) holding one
+    harmonic that plunges inside the year, at plunge_frac of the data, with
+    f_p ~ U[8, 30] mHz and t_c ~ logU[0.02, 1] yr; training tracks (5000, the
+    same law) plunge at the end of the data, so a basis shifted by whole
+    segments aligns the plunge with the end of any shorter duration."""
+    dt, n_sft = 10.0, 16384
+    n = int(round(3.15e7 / dt))
+    n_seg = n // n_sft
+    t_sft = n_sft * dt
+    gi = rng(cfg, stream, PURPOSE_INJECTION)
+    fp = gi.uniform(8e-3, 30e-3)
+    tc = math.exp(gi.uniform(math.log(0.02 * YEAR_S), math.log(1.0 * YEAR_S)))
+    phi0 = gi.uniform(0.0, 2.0 * math.pi)
+    t_inj = plunge_frac * n_seg * t_sft
+    tau = t_inj + tc
+    f0 = fp * (1.0 + t_inj / tc) ** (-0.375)                  # frequency at t = 0
+    x = coloured_noise(n, dt, psd_coloured, rng(cfg, stream, PURPOSE_NOISE))
+    inj = None
+    if snr is not None and snr > 0:
+        inj = dict(f0=f0, tau=tau, t_plunge=t_inj, f_plunge=fp, t_c=tc, snr=float(snr), phi0=phi0)
+        x = x + injection(n, dt, f0, tau, snr, psd_coloured, phi0, t_cut=t_inj)
+    t_mid = segment_midpoints(n_seg, t_sft)
+    tracks = plunge_tracks(5000, t_mid, n_seg * t_sft, (8e-3, 30e-3), (0.02 * YEAR_S, 1.0 * YEAR_S),
+                           rng(cfg, stream, PURPOSE_TRAINING))
+    return dict(cfg=cfg, stream=stream, dt=dt, n_sft=n_sft, x=x, psd_fn=psd_coloured,
+                psd=psd_on_bins(psd_coloured, n_sft, dt), tracks=tracks, K=8, injection=inj, t_mid=t_mid)
 
 
 def batched_streams(n_streams: int = 64, cfg: int = 3) -> list[dict]:

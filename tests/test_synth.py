@@ -85,3 +85,25 @@ def test_search_draws():
     a = synth.search_generation_draws(0, 1, 3, 64)
     b = synth.search_generation_draws(0, 1, 4, 64)
     assert not np.array_equal(a[0], b[0])            # generations draw independently
+
+
+def test_plunge_tracks_end_at_the_plunge():
+    t_mid = synth.segment_midpoints(192, 163840.0)
+    T = 192 * 163840.0
+    F = synth.plunge_tracks(50, t_mid, T, (8e-3, 30e-3), (0.02 * synth.YEAR_S, synth.YEAR_S), synth.rng(0, 0, 2))
+    assert F.shape == (50, 192)
+    assert np.all(np.diff(F, axis=1) > 0)                       # chirping up to the plunge
+    assert np.all(F[:, -1] <= 30e-3) and np.all(F[:, -1] >= 0.9 * 8e-3)
+    assert np.all(F < 0.45 / 10.0)                              # below Nyquist at dt = 10 s
+
+
+def test_progressive_stream_injection_stops_at_plunge():
+    st = synth.stream_progressive(stream=0, plunge_frac=0.7)
+    inj = st["injection"]
+    assert abs(inj["t_plunge"] - 0.7 * 192 * 163840.0) < 1.0
+    noise = synth.stream_progressive(stream=0, plunge_frac=0.7, snr=None)["x"]
+    h = st["x"] - noise
+    k = int(inj["t_plunge"] / st["dt"])
+    assert np.all(h[k + 1:] == 0.0) and np.any(h[:k] != 0.0)
+    assert np.isclose(synth.chirp_frequency(inj["t_plunge"] - 1e-6, inj["f0"], inj["tau"]), inj["f_plunge"],
+                      rtol=1e-9)
