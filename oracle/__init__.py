@@ -19,7 +19,9 @@ Each function is the plain definition of one step, written from the paper:
                       track-space differential-evolution step of Eq. (11),
                       the shifted basis and noise normalisation of the
                       progressive-duration search;
-* ``harmonics``    -- the multi-harmonic statistic proposed in Sec. IV.
+* ``harmonics``    -- the multi-harmonic statistic proposed in Sec. IV;
+* ``chirp``        -- the linear-chirp statistic of Sec. II B over 2P + 1 bins
+                      (Eqs. (4)-(7)) with the validity cut and cut-offs.
 
 Every function is pinned by the CPU tests against closed forms, brute force on
 tiny inputs and distributional laws (see the test modules); none is marked
@@ -29,11 +31,11 @@ from .sft import build_sfts, hann_periodic, sft_bin_frequencies
 from .basis import build_basis, BOX_Q_LO, BOX_Q_HI
 from .score import (score_tracks, track_positions, chosen_bins, near_tie_mask,
                     topk_order, score_tracks_exact, NEAR_TIE_BAND)
-from . import search, harmonics
+from . import search, harmonics, chirp
 
 __all__ = [
     "build_sfts", "hann_periodic", "sft_bin_frequencies",
     "build_basis", "BOX_Q_LO", "BOX_Q_HI",
     "score_tracks", "track_positions", "chosen_bins", "near_tie_mask", "topk_order",
-    "score_tracks_exact", "NEAR_TIE_BAND", "search", "harmonics",
+    "score_tracks_exact", "NEAR_TIE_BAND", "search", "harmonics", "chirp",
 ]

@@ -124,6 +124,33 @@ def test_harmonics_pins():
     pins_harmonics.check_harmonics_additive(ohm.score_harmonics)
 
 
+def test_chirp_template_against_bruteforce_dft():
+    import oracle.chirp as oc
+    from tests import pins_chirp
+    pins_chirp.check_template_bruteforce(oc.chirp_template_bins)
+    pins_chirp.check_template_no_derivative(oc.chirp_template_bins)
+
+
+def test_chirp_statistic_pins():
+    import oracle.chirp as oc
+    from tests import pins_chirp
+    pins_chirp.check_one_bin_is_nearest_bin_power(oc.score_chirp, oc.build_sfts_complex, oc.inverse_sqrt_psd)
+    pins_chirp.check_matched_chirp(oc.segment_statistic, oc.build_sfts_complex, oc.inverse_sqrt_psd,
+                                   oc.chirp_template_bins)
+    pins_chirp.check_track_derivatives(oc.track_derivatives)
+    pins_chirp.check_validity_and_cutoffs(oc.score_chirp, oc.build_sfts_complex, oc.inverse_sqrt_psd)
+
+
+def test_chirp_complex_sft_power_is_build_sfts():
+    import oracle.chirp as oc
+    g = np.random.default_rng(3)
+    x = g.standard_normal(5 * 600)
+    psd = g.uniform(1, 3, 301)
+    psd[7] = 0.0
+    Z = oc.build_sfts_complex(x, 2.0, 600, psd)
+    assert np.allclose(np.abs(Z) ** 2, oracle.build_sfts(x, 2.0, 600, psd), rtol=1e-12, atol=0)
+
+
 def test_oracle_is_isolated():
     """The oracle imports nothing from the HIP library package."""
     import ast, pathlib

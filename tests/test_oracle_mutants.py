@@ -373,3 +373,86 @@ def _hpos_drop_first(x, ratios):
 def test_harmonic_mutant_caught(fn, monkeypatch):
     monkeypatch.setattr(ohm, "harmonic_positions", fn)
     assert _caught(HARMONIC_PINS, ohm.score_harmonics), fn.__name__
+
+
+# ---------------------------------------------------------------- linear chirp (Sec. II B)
+import oracle.chirp as och
+from tests import pins_chirp
+
+_orig_template = och.chirp_template_bins
+_orig_segment = och.segment_statistic
+
+
+def _chirp_checks():
+    return [lambda: pins_chirp.check_template_bruteforce(och.chirp_template_bins),
+            lambda: pins_chirp.check_template_no_derivative(och.chirp_template_bins),
+            lambda: pins_chirp.check_one_bin_is_nearest_bin_power(och.score_chirp, och.build_sfts_complex,
+                                                                  och.inverse_sqrt_psd),
+            lambda: pins_chirp.check_matched_chirp(och.segment_statistic, och.build_sfts_complex,
+                                                   och.inverse_sqrt_psd, och.chirp_template_bins),
+            lambda: pins_chirp.check_track_derivatives(och.track_derivatives),
+            lambda: pins_chirp.check_validity_and_cutoffs(och.score_chirp, och.build_sfts_complex,
+                                                          och.inverse_sqrt_psd)]
+
+
+def _template_beta_sign(d0, beta, p):
+    return _orig_template(d0, -beta, p)
+
+
+def _template_rect(d0, beta, p):
+    m = np.arange(-p, p + 1)
+    u, wt = och._gauss_grid(abs(d0) + p + abs(beta) + 1.0)
+    g = wt * np.exp(1j * (2.0 * np.pi * d0 * u + np.pi * beta * u * u))
+    return np.exp(-2j * np.pi * np.outer(m, u)) @ g
+
+
+def _segment_no_sign(Z_row, isq, f, fdot, t_sft, p_half):
+    # the (-1)^k of the segment-start time origin dropped
+    orig = och.chirp_template_bins
+    k0 = int(np.rint(f * t_sft))
+    def tpl(d0, beta, p):
+        m = np.arange(-p, p + 1)
+        return orig(d0, beta, p) * np.where((k0 + m) % 2 == 0, 1.0, -1.0)
+    och.chirp_template_bins = tpl
+    try:
+        return _orig_segment(Z_row, isq, f, fdot, t_sft, p_half)
+    finally:
+        och.chirp_template_bins = orig
+
+
+def _segment_no_weight(Z_row, isq, f, fdot, t_sft, p_half):
+    return _orig_segment(Z_row, np.where(isq > 0, 1.0, 0.0), f, fdot, t_sft, p_half)
+
+
+def _derivative_forward(f, t_sft):
+    f = np.asarray(f, dtype=np.float64)
+    fd = np.empty_like(f)
+    fd[..., :-1] = (f[..., 1:] - f[..., :-1]) / t_sft
+    fd[..., -1] = fd[..., -2]
+    fdd = np.zeros_like(f)
+    return fd, fdd
+
+
+def _valid_T2(f, fdot, fddot, t_sft, f_min=och.F_MIN, fdot_min=och.FDOT_MIN):
+    return (np.abs(fddot) * t_sft ** 2 / 6.0 <= 1.0) & (f >= f_min) & (fdot >= fdot_min)
+
+
+def _valid_abs_fdot(f, fdot, fddot, t_sft, f_min=och.F_MIN, fdot_min=och.FDOT_MIN):
+    return (np.abs(fddot) * t_sft ** 3 / 6.0 <= 1.0) & (f >= f_min) & (np.abs(fdot) >= fdot_min)
+
+
+@pytest.mark.parametrize("attr,fn", [
+    ("chirp_template_bins", _template_beta_sign), ("chirp_template_bins", _template_rect),
+    ("segment_statistic", _segment_no_sign), ("segment_statistic", _segment_no_weight),
+    ("track_derivatives", _derivative_forward), ("segment_valid", _valid_T2), ("segment_valid", _valid_abs_fdot),
+])
+def test_chirp_mutant_caught(attr, fn, monkeypatch):
+    monkeypatch.setattr(och, attr, fn)
+    caught = False
+    for check in _chirp_checks():
+        try:
+            check()
+        except (AssertionError, ValueError, IndexError):
+            caught = True
+            break
+    assert caught, fn.__name__
