@@ -41,7 +41,11 @@ typedef enum {
   EMRI_EUNSUPPORTED = -5  /* a valid request the library does not implement      */
 } emri_status;
 
-typedef enum { EMRI_F32 = 0, EMRI_F16 = 1 } emri_pdtype;   /* power storage type */
+typedef enum {
+  EMRI_F32 = 0,           /* normalised power, FP32                                          */
+  EMRI_F16 = 1,           /* normalised power, FP16                                          */
+  EMRI_C32 = 2            /* whitened complex SFT, (re, im) FP32 pairs (linear-chirp statistic) */
+} emri_pdtype;
 
 /* A normalised-power spectrogram in device memory, owned by the caller.
  * Row alpha (segment alpha) holds P[alpha, b] for bins b = 0..n_bins-1 at
@@ -94,7 +98,11 @@ typedef struct {
  *              elements), out->row_pitch and out->dtype are read; n_seg, n_bins
  *              and t_sft are written.  Padding elements are written as 0.
  *              FP16 storage rounds to nearest (values above the FP16 range
- *              become +inf).
+ *              become +inf).  With dtype EMRI_C32 an element is the whitened
+ *              complex SFT Z[alpha, b] = X_b / sqrt((3 n_sft / 8) psd[b] / (2 dt))
+ *              as two FP32 values (re, im), so |Z|^2 is the power above; bins
+ *              with a non-positive or non-finite psd hold 0.  Only the
+ *              linear-chirp statistic (score_tracks_chirp) reads C32 data.
  */
 int build_sfts(const double *x, int64_t n_samples, double dt, int32_t n_sft,
                const double *psd, emri_power *out, void *hip_stream);
@@ -214,6 +222,50 @@ int score_tracks_harmonics(const emri_power *power, const double *f0, const doub
                            const float *coeffs, int64_t n_tmpl, int32_t n_harm, const double *ratios,
                            int32_t top_k, float *stat, float *topk_val, int64_t *topk_idx,
                            const score_opts *opts, void *workspace, size_t workspace_bytes, void *hip_stream);
+
+/*
+ * score_tracks_chirp -- the linear-chirp statistic of Sec. II B (Eqs. (4)-(7))
+ * over 2P + 1 bins, the paper's own statistic (score_tracks is its one-bin,
+ * zero-bandwidth limit).  Per template and segment alpha, with the track
+ * f[alpha] = f0[alpha] + sum_k c_k U[alpha, k] (FP64), fdot and fddot its
+ * second-order finite differences over the segment grid (central inside,
+ * one-sided fdot at the ends, the neighbour's fddot at the ends), k0 =
+ * rint(f T) inside the row (else the segment contributes nothing) and, over
+ * the bins k = k0 - P..k0 + P inside the row,
+ *     H_k      = R(f T - k, fdot T^2) (up to a factor common to all k),
+ *     R(d, b)  = int_{-1/2}^{1/2} cos^2(pi u) exp(2 pi i d u + i pi b u^2) du
+ *                (the SFT of the Hann-windowed unit linear chirp, Eqs. (4)-(5)),
+ *     S_alpha  = |sum_k conj(Z_k) H_k / sqrt(psd_k)|^2 / sum_k |H_k|^2 / psd_k
+ * ((max over phase of <d|h>)^2 / <h|h>, Eq. (6)-(7), without the constant
+ * 3/4 = 2 sum w^2 / N, so that P = 0 gives the nearest-bin power), and
+ *     S = sum over segments with |fddot| T^3 / 6 <= 1, f >= f_min and
+ *         fdot >= fdot_min of S_alpha    (Sec. II B validity cut, Sec. II D cut-offs).
+ * R is evaluated as the 256-point DFT of its Hann-windowed samples (relative
+ * error below 4e-7 for |fdot T^2| <= 60), in FP32; sums over bins in FP32
+ * per lane and FP64 across lanes, over segments in FP64; S stored FP32.
+ *
+ *   sfts     complex whitened SFTs from build_sfts with dtype EMRI_C32
+ *            (n_seg <= 2048)
+ *   psd      device FP64[n_bins]; bins with psd <= 0 or not finite take no part
+ *   f0, U, K, coeffs, n_tmpl, top_k, stat, topk_val, topk_idx  as in score_tracks
+ *   opts     NULL for P = 100, f_min = 10^-3.5 Hz, fdot_min = 1e-13 Hz/s;
+ *            pass -INFINITY to disable a cut-off; 0 <= p_half <= 100
+ *   workspace  score_tracks_chirp_workspace_size() bytes, 256-byte aligned
+ */
+typedef struct {
+  int32_t p_half;            /* P: the window is 2P + 1 bins                    */
+  int32_t pad;
+  double f_min;              /* Hz: segments below contribute nothing           */
+  double fdot_min;           /* Hz/s: segments below contribute nothing         */
+  int32_t reserved[4];       /* must be zero                                    */
+} chirp_opts;
+
+int score_tracks_chirp_workspace_size(const emri_power *sfts, int32_t K, int64_t n_tmpl, int32_t top_k,
+                                      int32_t stat_in_workspace, size_t *bytes);
+int score_tracks_chirp(const emri_power *sfts, const double *psd, const double *f0, const double *U, int32_t K,
+                       const float *coeffs, int64_t n_tmpl, int32_t top_k, float *stat, float *topk_val,
+                       int64_t *topk_idx, const chirp_opts *opts, void *workspace, size_t workspace_bytes,
+                       void *hip_stream);
 
 /*
  * Batched form: many scoring problems in one persistent launch.

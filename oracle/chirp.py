@@ -18,7 +18,9 @@ Definitions written out here (the readings are listed with each function):
       H_k = (-1)^k R(f T - k, fdot T^2),  R(d, b) = int_{-1/2}^{1/2} cos^2(pi u) exp(2 pi i d u + i pi b u^2) du
   (the common factor T/dt is dropped; (-1)^k because the DFT's time origin is
   the segment's start, the chirp's its midpoint);
-* per segment, with k0 = rint(f T) and the bins k0 - P..k0 + P inside the row,
+* per segment, with k0 = rint(f T) inside the row (else the segment
+  contributes nothing, as a position outside the row does in the nearest-bin
+  statistic) and the bins k0 - P..k0 + P inside the row,
       S_alpha = |sum_k conj(Z_k) H_k / sqrt(S_k)|^2 / sum_k |H_k|^2 / S_k ,
   which is (max over phase of <d|h>)^2 / <h|h> up to the constant 2 sum w^2 / N
   (= 3/4 for the Hann window), dropped so that with P = 0 the statistic is the
@@ -109,7 +111,11 @@ def segment_statistic(Z_row, isq, f: float, fdot: float, t_sft: float, p_half: i
     """S_alpha of one segment (FP64) for local frequency f and derivative fdot."""
     n_bins = Z_row.shape[0]
     x = f * t_sft
+    if not np.isfinite(x) or not (-0.5 <= x < n_bins - 0.5):
+        return 0.0                          # the central bin is outside the row
     k0 = int(np.rint(x))
+    if not 0 <= k0 < n_bins:
+        return 0.0
     m = np.arange(-p_half, p_half + 1)
     k = k0 + m
     inside = (k >= 0) & (k < n_bins)

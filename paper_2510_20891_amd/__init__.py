@@ -22,10 +22,10 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libemri.so")
 
-F32, F16 = 0, 1
+F32, F16, C32 = 0, 1, 2
 PLAIN, MIXED = 0, 1
 _PRECISIONS = {"plain": PLAIN, "mixed": MIXED}
-_DTYPES = {"f32": F32, "f16": F16}
+_DTYPES = {"f32": F32, "f16": F16, "c32": C32}
 MAX_K = 32
 MAX_TOPK = 4096
 
@@ -69,6 +69,11 @@ class _Chain(ctypes.Structure):
                 ("stat", _vp), ("n_walkers", _i32), ("k_min", _i32), ("k_max", _i32), ("reserved", _i32)]
 
 
+class _ChirpOpts(ctypes.Structure):
+    _fields_ = [("p_half", _i32), ("pad", _i32), ("f_min", ctypes.c_double), ("fdot_min", ctypes.c_double),
+                ("reserved", _i32 * 4)]
+
+
 class _SearchPlan(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_int64 * 40)]
 
@@ -86,6 +91,10 @@ SIGNATURES = {
     "score_tracks_harmonics": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _i32, _vp, _i64, _i32,
                                               ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp, _vp,
                                               ctypes.POINTER(_Opts), _vp, _sz, _vp]),
+    "score_tracks_chirp_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Power), _i32, _i64, _i32, _i32,
+                                                         ctypes.POINTER(_sz)]),
+    "score_tracks_chirp": (ctypes.c_int, [ctypes.POINTER(_Power), _vp, _vp, _vp, _i32, _vp, _i64, _i32, _vp, _vp,
+                                          _vp, ctypes.POINTER(_ChirpOpts), _vp, _sz, _vp]),
     "score_batched_workspace_size": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_sz)]),
     "score_batched_tile_options": (ctypes.c_int, [_i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "score_batched_plan": (ctypes.c_int, [ctypes.POINTER(_Problem), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp,
@@ -170,7 +179,7 @@ class Spectrogram:
     @property
     def dtype_code(self) -> int:
         import torch
-        return F16 if self.data.dtype == torch.float16 else F32
+        return {torch.float16: F16, torch.complex64: C32}.get(self.data.dtype, F32)
 
     def power(self):
         """The (n_seg, n_bins) view of the power without row padding."""
@@ -206,7 +215,7 @@ def build_sfts(x, dt: float, n_sft: int, psd, dtype: str = "f32", row_pitch: int
     n_bins = n_sft // 2 + 1
     n_seg = x.numel() // n_sft if n_sft > 0 else 0
     pitch = row_pitch or default_row_pitch(n_bins)
-    tdtype = torch.float32 if dtype == "f32" else torch.float16
+    tdtype = {"f32": torch.float32, "f16": torch.float16, "c32": torch.complex64}[dtype]
     data = torch.empty((n_seg, pitch), dtype=tdtype, device=x.device)
     pw = _Power(data.data_ptr() if data.numel() else 0, 0, 0, pitch, _DTYPES[dtype], 0.0)
     _check("build_sfts", load().build_sfts(_ptr(x), x.numel(), float(dt), int(n_sft), _ptr(psd),
@@ -377,6 +386,50 @@ def score_tracks_harmonics(spec: Spectrogram, f0, U, coeffs, ratios, top_k: int,
     pw = spec._struct()
     _check("score_tracks_harmonics", load().score_tracks_harmonics(
         ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, len(r), rr,
+        int(top_k), _ptr(res.get("stat")), _ptr(res["topk_val"]) if top_k else None,
+        _ptr(res["topk_idx"]) if top_k else None, ctypes.byref(opts), ws_ptr, ws_len, int(s.cuda_stream)))
+    return res
+
+
+CHIRP_F_MIN = 10.0 ** -3.5
+CHIRP_FDOT_MIN = 1e-13
+
+
+def score_tracks_chirp(sfts: Spectrogram, psd, f0, U, coeffs, top_k: int, *, p_half: int = 100,
+                       f_min: float = CHIRP_F_MIN, fdot_min: float = CHIRP_FDOT_MIN, want_stat: bool = True,
+                       out: dict | None = None, workspace: Workspace | None = None, stream=None) -> dict:
+    """The linear-chirp statistic over 2 p_half + 1 bins (complex SFTs from
+    build_sfts(..., dtype="c32"), the FP64 PSD on the bins); see include/emri.h."""
+    import torch
+    _require_cuda(psd, torch.float64, "psd")
+    _require_cuda(f0, torch.float64, "f0")
+    _require_cuda(U, torch.float64, "U")
+    _require_cuda(coeffs, torch.float32, "coeffs")
+    if sfts.dtype_code != C32:
+        raise TypeError("score_tracks_chirp needs complex SFTs (dtype c32)")
+    K = int(U.shape[1]) if U.dim() == 2 else 0
+    n_tmpl = int(coeffs.shape[0])
+    if coeffs.dim() != 2 or coeffs.shape[1] != K:
+        raise ValueError("coeffs must be (n_tmpl, K)")
+    dev = coeffs.device
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    out = {} if out is None else out
+    res = {}
+    with torch.cuda.stream(s):
+        if want_stat:
+            res["stat"] = out.get("stat") if out.get("stat") is not None else torch.empty(n_tmpl, dtype=torch.float32, device=dev)
+        res["topk_val"] = out.get("topk_val") if out.get("topk_val") is not None else torch.empty(top_k, dtype=torch.float32, device=dev)
+        res["topk_idx"] = out.get("topk_idx") if out.get("topk_idx") is not None else torch.empty(top_k, dtype=torch.int64, device=dev)
+    pw = sfts._struct()
+    lib = load()
+    nb = ctypes.c_size_t(0)
+    _check("score_tracks_chirp_workspace_size", lib.score_tracks_chirp_workspace_size(
+        ctypes.byref(pw), K, n_tmpl, int(top_k), int(not want_stat), ctypes.byref(nb)))
+    ws = workspace if workspace is not None else default_workspace(dev, s)
+    ws_ptr, ws_len = ws.get(int(nb.value), dev, s)
+    opts = _ChirpOpts(int(p_half), 0, float(f_min), float(fdot_min))
+    _check("score_tracks_chirp", lib.score_tracks_chirp(
+        ctypes.byref(pw), _ptr(psd), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl,
         int(top_k), _ptr(res.get("stat")), _ptr(res["topk_val"]) if top_k else None,
         _ptr(res["topk_idx"]) if top_k else None, ctypes.byref(opts), ws_ptr, ws_len, int(s.cuda_stream)))
     return res
@@ -599,5 +652,5 @@ def search_noise_moments(best, stream=None):
     return mean, sd
 
 
-__all__ = ["score_tracks_harmonics", "Chain", "SearchPlan", "search_seed", "search_noise_moments", "Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
+__all__ = ["score_tracks_chirp", "score_tracks_harmonics", "Chain", "SearchPlan", "search_seed", "search_noise_moments", "Problem", "BatchPlan", "score_tracks_noalloc", "score_tracks_noalloc_limit", "batched_tile_options", "load", "build_sfts", "build_basis", "score_tracks", "score_tracks_workspace_size",
            "Spectrogram", "spectrogram_from_power", "Workspace", "default_workspace", "EmriError", "F32", "F16", "LIB_PATH"]

@@ -135,6 +135,32 @@ __device__ __forceinline__ __half to_storage<__half>(double v) {
   return __float2half(f);
 }
 
+// Power output (FP32 or FP16 element per bin), or with PT = float2 the whitened
+// complex SFT X_b / sqrt(sum w^2 S_b / (2 dt)) as (re, im) FP32 pairs.
+template <typename PT>
+__device__ __forceinline__ PT sft_store(double xr, double xi, double scale2);
+template <>
+__device__ __forceinline__ float sft_store<float>(double xr, double xi, double scale2) {
+  return to_storage<float>((xr * xr + xi * xi) * scale2);
+}
+template <>
+__device__ __forceinline__ __half sft_store<__half>(double xr, double xi, double scale2) {
+  return to_storage<__half>((xr * xr + xi * xi) * scale2);
+}
+template <>
+__device__ __forceinline__ float2 sft_store<float2>(double xr, double xi, double scale2) {
+  const double s = __builtin_sqrt(scale2);
+  return make_float2((float)(xr * s), (float)(xi * s));
+}
+template <typename PT>
+__device__ __forceinline__ PT sft_zero();
+template <>
+__device__ __forceinline__ float sft_zero<float>() { return 0.0f; }
+template <>
+__device__ __forceinline__ __half sft_zero<__half>() { return to_storage<__half>(0.0); }
+template <>
+__device__ __forceinline__ float2 sft_zero<float2>() { return make_float2(0.0f, 0.0f); }
+
 template <typename PT>
 __global__ __launch_bounds__(SFT_THREADS) void sft_kernel(const double *__restrict__ x, int n_sft, double dt,
                                                            const double *__restrict__ psd, PT *__restrict__ out,
@@ -166,7 +192,7 @@ __global__ __launch_bounds__(SFT_THREADS) void sft_kernel(const double *__restri
   const double sum_w2 = 0.375 * (double)N;
   PT *row = out + (size_t)blockIdx.x * (size_t)row_pitch;
   for (int b = threadIdx.x; b < row_pitch; b += SFT_THREADS) {
-    double p = 0.0;
+    PT p = sft_zero<PT>();
     if (b <= M) {
       const double s_b = psd[b];
       if (s_b > 0.0 && s_b <= 1.7976931348623157e308) {
@@ -180,10 +206,10 @@ __global__ __launch_bounds__(SFT_THREADS) void sft_kernel(const double *__restri
         sincospi(-(double)b / (double)M, &s, &c);
         const double2 t = cmul(o, make_double2(c, s));
         const double xr = e.x + t.x, xi = e.y + t.y;
-        p = (xr * xr + xi * xi) * (2.0 * dt) / (sum_w2 * s_b);
+        p = sft_store<PT>(xr, xi, (2.0 * dt) / (sum_w2 * s_b));
       }
     }
-    row[b] = to_storage<PT>(p);
+    row[b] = p;
   }
 }
 
@@ -215,7 +241,8 @@ extern "C" int build_sfts(const double *x, int64_t n_samples, double dt, int32_t
   if (n_samples < 0) return fail(EMRI_EINVAL, "n_samples < 0");
   if (!(dt > 0.0) || !(dt < 1e300)) return fail(EMRI_EINVAL, "dt must be finite and > 0");
   if (n_sft < 4 || (n_sft & 1)) return fail(EMRI_EINVAL, "n_sft must be even and >= 4");
-  if (out->dtype != EMRI_F32 && out->dtype != EMRI_F16) return fail(EMRI_EINVAL, "unknown power dtype %d", out->dtype);
+  if (out->dtype != EMRI_F32 && out->dtype != EMRI_F16 && out->dtype != EMRI_C32)
+    return fail(EMRI_EINVAL, "unknown power dtype %d", out->dtype);
   const int n_bins = n_sft / 2 + 1;
   if (out->row_pitch < n_bins || (out->row_pitch % 8) != 0)
     return fail(EMRI_EINVAL, "row_pitch %d must be a multiple of 8 and >= n_bins %d", out->row_pitch, n_bins);
@@ -241,6 +268,14 @@ extern "C" int build_sfts(const double *x, int64_t n_samples, double dt, int32_t
     if (err == hipSuccess) {
       hipLaunchKernelGGL(sft_kernel<float>, dim3((unsigned)n_seg), dim3(SFT_THREADS), lds, stream, x, n_sft, dt,
                          psd, reinterpret_cast<float *>(out->data), out->row_pitch, plan);
+      err = hipGetLastError();
+    }
+  } else if (out->dtype == EMRI_C32) {
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(&sft_kernel<float2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err == hipSuccess) {
+      hipLaunchKernelGGL(sft_kernel<float2>, dim3((unsigned)n_seg), dim3(SFT_THREADS), lds, stream, x, n_sft, dt,
+                         psd, reinterpret_cast<float2 *>(out->data), out->row_pitch, plan);
       err = hipGetLastError();
     }
   } else {

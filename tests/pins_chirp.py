@@ -74,6 +74,17 @@ def check_one_bin_is_nearest_bin_power(score_chirp, build_sfts_complex, inverse_
     ok = res["valid"]
     assert np.allclose(res["per_segment"][ok], want[ok], rtol=1e-12, atol=0)
     assert ok.sum() > 0
+    # a central bin outside the row: no contribution, even where window bins reach into the row
+    Zr = Z[0]
+    n_bins = Zr.shape[0]
+    assert segment_statistic_of(score_chirp)(Zr, inverse_sqrt_psd(psd), (n_bins + 3) / T, 0.0, T, 10) == 0.0
+    assert segment_statistic_of(score_chirp)(Zr, inverse_sqrt_psd(psd), -4.0 / T, 0.0, T, 10) == 0.0
+    assert segment_statistic_of(score_chirp)(Zr, inverse_sqrt_psd(psd), (n_bins - 2) / T, 0.0, T, 10) > 0.0
+
+
+def segment_statistic_of(score_chirp):
+    import importlib
+    return importlib.import_module(score_chirp.__module__).segment_statistic
 
 
 def check_matched_chirp(segment_statistic, build_sfts_complex, inverse_sqrt_psd, chirp_template_bins):
