@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FMA)
 
 
 def progress(msg: str) -> None:
@@ -353,6 +354,55 @@ def harmonics_form(st, n: int = 10_000_000, reps: int = 5) -> dict:
                          "algorithmic_bytes_per_launch": b_eff}}
 
 
+CHIRP_M = 256                       # template FFT length of the chirp kernel
+
+
+def chirp_flops_per_eval(p_half: int = 100) -> int:
+    """Algorithmic FP32 flops of one (template, segment) linear-chirp
+    evaluation: the template's M-point FFT at 5 M log2 M, its M windowed
+    samples at 6 flops each (sine and cosine not counted), and 14 flops per
+    window bin (PSD weighting, the complex inner product and |H|^2)."""
+    return 5 * CHIRP_M * 8 + 6 * CHIRP_M + 14 * (2 * p_half + 1)
+
+
+def chirp_form(st, n: int = 1_000_000, reps: int = 3) -> dict:
+    """The linear-chirp statistic (Sec. II B) on the one-year stream's
+    whitened complex SFTs: 1e6 templates, K = 8, 2P + 1 = 201 bins, cut-offs
+    of Sec. II D, top-256.  Arithmetic-bound: the roofline counts
+    chirp_flops_per_eval flops per template and segment against the FP32
+    vector peak."""
+    import torch
+    import paper_2510_20891_amd as emri
+    dev = torch.device("cuda:0")
+    K, top_k = 8, 256
+    f0, U, sv, lo, hi = emri.build_basis(st["tracks"], K)
+    f0_d, U_d = torch.from_numpy(f0).to(dev), torch.from_numpy(U).to(dev)
+    C_d = torch.from_numpy(synth.coefficients(1, 0, n, lo, hi)).to(dev)
+    psd_d = torch.from_numpy(st["psd"]).to(dev)
+    spec = emri.build_sfts(torch.from_numpy(st["x"]).to(dev), st["dt"], st["n_sft"], psd_d, dtype="c32")
+    ws = emri.Workspace()
+    out = {"stat": torch.empty(n, dtype=torch.float32, device=dev),
+           "topk_val": torch.empty(top_k, dtype=torch.float32, device=dev),
+           "topk_idx": torch.empty(top_k, dtype=torch.int64, device=dev)}
+    ms = _event_ms(lambda: emri.score_tracks_chirp(spec, psd_d, f0_d, U_d, C_d, top_k, out=out, workspace=ws), reps)
+    ms0 = _event_ms(lambda: emri.score_tracks_chirp(spec, psd_d, f0_d, U_d, C_d, 0, out=out, workspace=ws), reps)
+    n_seg = spec.n_seg
+    flops = chirp_flops_per_eval() * n * n_seg
+    achieved = flops / (ms0 * 1e-3) / 1e12
+    progress(f"chirp form: {ms:.1f} ms for {n} templates ({achieved:.1f} TFLOP/s)")
+    return {"workload": f"one-year stream's complex SFTs ({n_seg} x {spec.n_bins}), {n} templates, K = {K}, "
+                        f"201-bin linear-chirp statistic, f >= 10^-3.5 Hz, fdot >= 1e-13 Hz/s, top-{top_k}",
+            "ms": ms, "kernel_ms": ms0,
+            "evals_per_s": n * n_seg / (ms * 1e-3),
+            "templates_per_s": n / (ms * 1e-3),
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                         "algorithmic_flops_per_eval": chirp_flops_per_eval(),
+                         "algorithmic_flops_per_launch": flops},
+            "paper_context": "about 1.1 h for ~1e7 evaluations of the 201-bin statistic in the search of Sec. II D "
+                             "on one unnamed GPU"}
+
+
 def search_form(n_gen: int = 525, n_walk: int = 512, n_draw: int = 1024, n_chunks: int = 48,
                 n_noise: int = 8, reps: int = 3) -> dict:
     """The population search of Sec. II D over progressive durations, on a
@@ -463,9 +513,9 @@ def main() -> int:
     ap.add_argument("--templates", type=int, default=10_000_000)
     ap.add_argument("--cpu-sample", type=int, default=1 << 22)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--forms", default="precision,batched,serving,search,harmonics",
+    ap.add_argument("--forms", default="precision,batched,serving,search,harmonics,chirp",
                     help="comma-separated forms measured after the headline "
-                         "(precision, batched, serving, search, harmonics, or none)")
+                         "(precision, batched, serving, search, harmonics, chirp, or none)")
     ap.add_argument("--serve-seconds", type=float, default=32.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference for traffic counters)")
@@ -591,7 +641,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         runners = {"precision": lambda: precision_form(st), "batched": batched_form,
                    "serving": lambda: serving_form(args.serve_seconds), "search": search_form,
-                   "harmonics": lambda: harmonics_form(st)}
+                   "harmonics": lambda: harmonics_form(st), "chirp": lambda: chirp_form(st)}
         line["forms"] = {f: runners[f]() for f in forms}
     print(json.dumps(line), flush=True)
     return 0

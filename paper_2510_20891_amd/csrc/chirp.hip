@@ -5,22 +5,29 @@
 // whitened data SFT is summed over the segments that pass the validity cut
 // (|fddot| T^3 / 6 <= 1) and the cut-offs of Sec. II D.
 //
-// Per template (one wave) and segment:
-//   * the track f[alpha] = f0 + sum_k c_k U[alpha, k] (FP64) is built once per
-//     template in LDS; fdot and fddot are second-order finite differences
-//     (central inside, one-sided at the ends for fdot, the neighbour's fddot
-//     at the ends);
+// Per template (one wave):
+//   * segments are taken 64 at a time, one per lane: the track values
+//     f0 + sum_k c_k U[., k] (FP64) at the segment and its neighbours give f,
+//     fdot and fddot (second-order finite differences: central inside,
+//     one-sided at the ends for fdot, the neighbour's fddot at the ends), the
+//     validity cut, k0 = rint(f T), d0 = f T - k0 and b = fdot T^2; the
+//     segments that contribute are compacted by a ballot and taken one after
+//     another, their parameters read from the owning lane;
 //   * the template SFT of the unit chirp, Hann-windowed,
 //         H_{k0 + j} ~ R(d0 - j, b),  R(d, b) = int cos^2(pi u) e^{2 pi i d u + i pi b u^2} du,
-//     d0 = f T - k0, b = fdot T^2, is the M = 256-point DFT of its samples
+//     is the M = 256-point DFT of its samples
 //     g_m = sin^2(pi m / M) e^{i pi (b u^2 + 2 d0 u)}, u = m / M - 1/2 (up to a
 //     common factor; the integrand vanishes smoothly at both ends, so the
 //     sum converges like the integral's aliased tail: relative error below
-//     4e-7 for |b| <= 60 and P = 100), by a four-pass radix-4 Stockham FFT in
-//     the wave's LDS (one butterfly per lane per pass), FP32;
+//     4e-7 for |b| <= 60 and P = 100), by a four-pass radix-4 Stockham FFT,
+//     FP32: each lane holds the samples m = lane + 64 q, which are the inputs
+//     of its first butterfly, and keeps the outputs j = lane + 64 q of its
+//     last; the two middle exchanges go through the wave's LDS buffer (padded
+//     against bank conflicts), twiddles and window stay in registers;
 //   * S_alpha = |sum_k conj(Z_k) H_k / sqrt(S_k)|^2 / sum_k |H_k|^2 / S_k over
-//     the window's bins inside the row (FP32 products, FP64 cross-lane sums),
-//     0 when the central bin rint(f T) is outside the row;
+//     the window's bins inside the row (FP32 products and sums within each
+//     row of 16 lanes, FP64 across rows), 0 when the central bin rint(f T)
+//     is outside the row;
 //   * S = sum of S_alpha over valid segments, FP64, stored FP32.
 #include <hip/hip_runtime.h>
 
@@ -35,14 +42,17 @@ namespace emri {
 namespace {
 
 constexpr int CH_M = 256;            // template samples (FFT length)
-constexpr int CH_QUARTER = CH_M / 4; // butterflies per radix-4 pass = lanes of a wave
 constexpr int CH_WAVES = 4;          // templates per workgroup
 constexpr int CH_THREADS = 64 * CH_WAVES;
 constexpr int CH_MAX_P = 100;        // 2P + 1 <= 201 bins
-constexpr int CH_MAX_SEG = 2048;     // track of every wave's template in LDS
-constexpr int CH_WIN = 2 * CH_MAX_P + 1;
-static_assert(CH_QUARTER == 64, "one butterfly per lane");
-static_assert((CH_WIN + 63) / 64 <= 4, "window bins per lane");
+constexpr int CH_MAX_SEG = 2048;
+static_assert(CH_M == 4 * 64, "four samples per lane");
+static_assert(CH_MAX_P < CH_M / 2, "window within the FFT's unaliased bins");
+
+// LDS slot of FFT element i: one float2 of padding after every four keeps
+// each pass's writes and reads within two-way bank conflicts.
+constexpr int lds_slot(int i) { return i + (i >> 2); }
+constexpr int CH_LDS = lds_slot(CH_M - 1) + 1;
 
 struct ChirpParams {
   const float2 *Z;            // n_seg rows x pitch bins
@@ -56,8 +66,20 @@ struct ChirpParams {
   int p_half, pad;
 };
 
-__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// y_r = sum_q v_q e^{-2 pi i q r / 4}
+__device__ __forceinline__ void butterfly4(float2 v[4]) {
+  const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
+  const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
+  const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
+  const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
+  v[0] = make_float2(s02.x + s13.x, s02.y + s13.y);
+  v[1] = make_float2(d02.x + d13.y, d02.y - d13.x);          // d02 - i d13
+  v[2] = make_float2(s02.x - s13.x, s02.y - s13.y);
+  v[3] = make_float2(d02.x - d13.y, d02.y + d13.x);          // d02 + i d13
 }
 
 __device__ __forceinline__ void lds_wave_sync() {
@@ -65,41 +87,28 @@ __device__ __forceinline__ void lds_wave_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-// Forward DFT of the wave's 256 samples in src (result in src after four
-// passes that alternate src / dst); tw[m] = e^{-2 pi i m / 256}.
-__device__ __forceinline__ float2 *fft256(float2 *src, float2 *dst, const float2 *tw, int lane) {
-  int Ns = 1;
-#pragma unroll
-  for (int pass = 0; pass < 4; ++pass) {
-    const int k = lane % Ns;
-    float2 v[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float2 x = src[lane + r * CH_QUARTER];
-      v[r] = r == 0 ? x : cmulf(x, tw[(r * k * (CH_M / (4 * Ns))) & (CH_M - 1)]);
-    }
-    const float2 s02 = make_float2(v[0].x + v[2].x, v[0].y + v[2].y);
-    const float2 d02 = make_float2(v[0].x - v[2].x, v[0].y - v[2].y);
-    const float2 s13 = make_float2(v[1].x + v[3].x, v[1].y + v[3].y);
-    const float2 d13 = make_float2(v[1].x - v[3].x, v[1].y - v[3].y);
-    const int base = (lane / Ns) * 4 * Ns + k;
-    dst[base] = make_float2(s02.x + s13.x, s02.y + s13.y);
-    dst[base + Ns] = make_float2(d02.x + d13.y, d02.y - d13.x);          // a - i b - c + i d
-    dst[base + 2 * Ns] = make_float2(s02.x - s13.x, s02.y - s13.y);
-    dst[base + 3 * Ns] = make_float2(d02.x - d13.y, d02.y + d13.x);      // a + i b - c - i d
-    lds_wave_sync();
-    float2 *t = src;
-    src = dst;
-    dst = t;
-    Ns *= 4;
-  }
-  return src;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Sum over the wave: FP32 within each row of 16 lanes (quad swaps, then the
+// half-row and row mirrors), FP64 over the four row sums.
+__device__ __forceinline__ double wave_total(float v) {
+  v += dpp<0xB1>(v);                   // quad_perm [1, 0, 3, 2]
+  v += dpp<0x4E>(v);                   // quad_perm [2, 3, 0, 1]
+  v += dpp<0x141>(v);                  // row_half_mirror
+  v += dpp<0x140>(v);                  // row_mirror: every lane holds its row's sum
+  const int b = __float_as_int(v);
+  const double r0 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 0));
+  const double r1 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 16));
+  const double r2 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 32));
+  const double r3 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 constexpr int CH_RESET_PARTS = 8;
@@ -120,93 +129,157 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_prep_kernel(const double *__
 }
 
 __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) {
-  __shared__ float2 tw[CH_M];
-  __shared__ float win[CH_M];
-  __shared__ float2 buf[CH_WAVES][2][CH_M];
-  extern __shared__ double track_lds[];
-  const int wave = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  for (int m = threadIdx.x; m < CH_M; m += CH_THREADS) {
-    double s, c;
-    sincospi(-2.0 * (double)m / CH_M, &s, &c);
-    tw[m] = make_float2((float)c, (float)s);
-    const double w = sinpi((double)m / CH_M);
-    win[m] = (float)(w * w);
-  }
+  __shared__ float2 lds[CH_WAVES][CH_LDS];
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = (int)(threadIdx.x & 63);
   const int64_t j = (int64_t)blockIdx.x * CH_WAVES + wave;
-  const bool live = j < p.n_tmpl;
-  double *track = track_lds + (size_t)wave * p.n_seg;
-  if (live) {
-    for (int a = lane; a < p.n_seg; a += 64) {
-      double f = p.f0[a];
-      for (int k = 0; k < p.K; ++k) f = __builtin_fma((double)p.coeffs[(size_t)j * p.K + k], p.U[(size_t)a * p.K + k], f);
-      track[a] = f;
+  if (j >= p.n_tmpl) return;           // no block-wide barrier in this kernel
+  float2 *buf = lds[wave];
+
+  // lane constants: window and sample offsets, twiddles of passes 1..3,
+  // LDS slots of each pass, window offsets j of the lane's outputs
+  float win[4], uq[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = lane + 64 * q;
+    const double w = sinpi((double)m / CH_M);
+    win[q] = (float)(w * w);
+    uq[q] = (float)m * (1.0f / CH_M) - 0.5f;
+  }
+  float2 tw[3][3];
+#pragma unroll
+  for (int ps = 1; ps < 4; ++ps) {
+    const int ns = 1 << (2 * ps);
+    const int k = lane & (ns - 1);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+      double sn, cs;
+      sincospi(-2.0 * (double)(r * k) / (double)(4 * ns), &sn, &cs);
+      tw[ps - 1][r - 1] = make_float2((float)cs, (float)sn);
     }
   }
-  __syncthreads();                     // tables and tracks; no block-wide barrier follows
-  if (!live) return;
+  const int rd = lds_slot(lane);                                        // + 80 r: element lane + 64 r
+  const int wr0 = lds_slot(4 * lane);                                   // + r: element 4 lane + r
+  const int wr1 = lds_slot(16 * (lane >> 2) + (lane & 3));              // + 5 r: element ... + 4 r
+  const int wr2 = lds_slot(64 * (lane >> 4) + (lane & 15));             // + 20 r: element ... + 16 r
+  int jo[4];
+  bool in_win[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    jo[r] = lane + 64 * r - (r >= 2 ? CH_M : 0);                        // output lane + 64 r is bin offset jo
+    in_win[r] = jo[r] >= -p.p_half && jo[r] <= p.p_half;
+  }
+
   const double T = p.t_sft;
-  const int n = p.n_seg;
+  const int n = p.n_seg, K = p.K;
+  const float *cj = p.coeffs + (size_t)j * K;
   double total = 0.0;
-  for (int a = 0; a < n; ++a) {
-    // local frequency and its derivatives (wave-uniform)
-    const double fa = track[a];
-    double fd = 0.0, fdd = 0.0;
-    if (n >= 3) {
-      if (a == 0) {
-        fd = (-3.0 * track[0] + 4.0 * track[1] - track[2]) / (2.0 * T);
-      } else if (a == n - 1) {
-        fd = (3.0 * track[n - 1] - 4.0 * track[n - 2] + track[n - 3]) / (2.0 * T);
+  for (int base = 0; base < n; base += 64) {
+    // ---- this chunk's segment parameters, one segment per lane ----
+    const int a = base + lane;
+    bool use = false;
+    int k0v = 0;
+    float d0v = 0.0f, bv = 0.0f;
+    if (a < n) {
+      auto track = [&](int i) {
+        double f = p.f0[i];
+        for (int k = 0; k < K; ++k) f = __builtin_fma((double)cj[k], p.U[(size_t)i * K + k], f);
+        return f;
+      };
+      double fa, fd = 0.0, fdd = 0.0;
+      if (n >= 3) {
+        const int c = a < 1 ? 1 : (a > n - 2 ? n - 2 : a);
+        const double fm = track(c - 1), fc = track(c), fp = track(c + 1);
+        if (a == 0) {
+          fa = fm;
+          fd = (-3.0 * fm + 4.0 * fc - fp) / (2.0 * T);
+        } else if (a == n - 1) {
+          fa = fp;
+          fd = (3.0 * fp - 4.0 * fc + fm) / (2.0 * T);
+        } else {
+          fa = fc;
+          fd = (fp - fm) / (2.0 * T);
+        }
+        fdd = (fp - 2.0 * fc + fm) / (T * T);
+      } else if (n == 2) {
+        const double g0 = track(0), g1 = track(1);
+        fa = a == 0 ? g0 : g1;
+        fd = (g1 - g0) / T;
       } else {
-        fd = (track[a + 1] - track[a - 1]) / (2.0 * T);
+        fa = track(0);
       }
-      const int c = a == 0 ? 1 : (a == n - 1 ? n - 2 : a);
-      fdd = (track[c + 1] - 2.0 * track[c] + track[c - 1]) / (T * T);
-    } else if (n == 2) {
-      fd = (track[1] - track[0]) / T;
-    }
-    const bool valid = __builtin_fabs(fdd) * T * T * T / 6.0 <= 1.0 && fa >= p.f_min && fd >= p.fdot_min;
-    if (!valid) continue;
-    const double x = fa * T;
-    if (!(__builtin_fabs(x) < 1e9)) continue;          // far outside any row
-    const double k0d = __builtin_rint(x);
-    const int k0 = (int)k0d;
-    if (k0 < 0 || k0 >= p.n_bins) continue;           // central bin outside the row: no contribution
-    const float d0 = (float)(x - k0d);
-    const float beta = (float)(fd * T * T);
-    // template samples, Hann-windowed (lane holds m = lane + 64 q)
-    float2 *s0 = buf[wave][0], *s1 = buf[wave][1];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = lane + 64 * q;
-      const float u = (float)m * (1.0f / CH_M) - 0.5f;
-      const float ph = beta * u * u + 2.0f * d0 * u;            // phase / pi
-      float sn, cs;
-      sincospif(ph, &sn, &cs);
-      s0[m] = make_float2(win[m] * cs, win[m] * sn);
-    }
-    lds_wave_sync();
-    const float2 *G = fft256(s0, s1, tw, lane);
-    // window sums
-    float nr = 0.0f, ni = 0.0f, dn = 0.0f;
-    const size_t row = (size_t)a * p.pitch;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int jj = lane + 64 * q;
-      const int jo = jj - p.p_half;                                  // offset from k0
-      const int k = k0 + jo;
-      if (jj <= 2 * p.p_half && k >= 0 && k < p.n_bins) {
-        const float2 h = G[jo & (CH_M - 1)];
-        const float s = p.isq[k];
-        const float2 z = p.Z[row + k];
-        const float hr = h.x * s, hi = h.y * s;
-        nr += z.x * hr + z.y * hi;                                   // conj(z) * h
-        ni += z.x * hi - z.y * hr;
-        dn += hr * hr + hi * hi;
+      const bool valid = __builtin_fabs(fdd) * T * T * T / 6.0 <= 1.0 && fa >= p.f_min && fd >= p.fdot_min;
+      const double x = fa * T;
+      if (valid && __builtin_fabs(x) < 1e9) {                           // else far outside any row
+        const double k0d = __builtin_rint(x);
+        k0v = (int)k0d;
+        use = k0v >= 0 && k0v < p.n_bins;                               // central bin outside the row: no contribution
+        d0v = (float)(x - k0d);
+        bv = (float)(fd * T * T);
       }
     }
-    const double NR = wave_sum((double)nr), NI = wave_sum((double)ni), DN = wave_sum((double)dn);
-    if (DN > 0.0) total += (NR * NR + NI * NI) / DN;
-    lds_wave_sync();                   // the next segment's samples overwrite G
+    uint64_t todo = __ballot(use);
+    // ---- the chunk's contributing segments, one after another ----
+    while (todo) {
+      const int l = __builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int k0 = __builtin_amdgcn_readlane(k0v, l);
+      const float d0 = readlane_f(d0v, l), beta = readlane_f(bv, l);
+      const float2 *zrow = p.Z + (size_t)(base + l) * p.pitch;
+      // samples (lane holds m = lane + 64 q) and the first butterfly
+      float2 v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float ph = uq[q] * fmaf(beta, uq[q], 2.0f * d0);         // phase / pi
+        float sn, cs;
+        sincospif(ph, &sn, &cs);
+        v[q] = make_float2(win[q] * cs, win[q] * sn);
+      }
+      butterfly4(v);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[wr0 + r] = v[r];
+      lds_wave_sync();
+      // pass 1 (stride 4) and pass 2 (stride 16), in place
+#pragma unroll
+      for (int ps = 1; ps < 3; ++ps) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = buf[rd + 80 * r];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) v[r] = cmul(v[r], tw[ps - 1][r - 1]);
+        butterfly4(v);
+        if (ps == 1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) buf[wr1 + 5 * r] = v[r];
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) buf[wr2 + 20 * r] = v[r];
+        }
+        lds_wave_sync();
+      }
+      // pass 3 (stride 64): outputs j = lane + 64 r stay in the lane
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = buf[rd + 80 * r];
+#pragma unroll
+      for (int r = 1; r < 4; ++r) v[r] = cmul(v[r], tw[2][r - 1]);
+      butterfly4(v);
+      // window sums over the lane's bins k0 + jo[r]
+      float nr = 0.0f, ni = 0.0f, dn = 0.0f;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = k0 + jo[r];
+        if (in_win[r] && (unsigned)k < (unsigned)p.n_bins) {
+          const float s = p.isq[k];
+          const float2 z = zrow[k];
+          const float hr = v[r].x * s, hi = v[r].y * s;
+          nr = fmaf(z.x, hr, fmaf(z.y, hi, nr));                        // conj(z) * h
+          ni = fmaf(z.x, hi, fmaf(-z.y, hr, ni));
+          dn = fmaf(hr, hr, fmaf(hi, hi, dn));
+        }
+      }
+      const double NR = wave_total(nr), NI = wave_total(ni), DN = wave_total(dn);
+      if (DN > 0.0) total += (NR * NR + NI * NI) / DN;
+      asm volatile("" ::: "memory");   // the next segment's first writes follow this segment's last reads
+    }
   }
   if (lane == 0) p.stat[j] = (float)total;
 }
@@ -324,14 +397,9 @@ extern "C" int score_tracks_chirp(const emri_power *sfts, const double *psd, con
     p.n_bins = sfts->n_bins;
     p.K = K;
     p.p_half = o.p_half;
-    const size_t lds = sizeof(double) * (size_t)CH_WAVES * (size_t)(sfts->n_seg > 0 ? sfts->n_seg : 1);
-    err = hipFuncSetAttribute(reinterpret_cast<const void *>(&chirp_score_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (err == hipSuccess) {
-      hipLaunchKernelGGL(chirp_score_kernel, dim3((unsigned)((n_tmpl + CH_WAVES - 1) / CH_WAVES)),
-                         dim3(CH_THREADS), lds, stream, p);
-      err = hipGetLastError();
-    }
+    hipLaunchKernelGGL(chirp_score_kernel, dim3((unsigned)((n_tmpl + CH_WAVES - 1) / CH_WAVES)), dim3(CH_THREADS), 0,
+                       stream, p);
+    err = hipGetLastError();
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "chirp launch: %s", hipGetErrorString(err));
   }
   if (top_k > 0) {
