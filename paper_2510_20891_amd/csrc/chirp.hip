@@ -25,9 +25,9 @@
 //     last; the two middle exchanges go through the wave's LDS buffer (padded
 //     against bank conflicts), twiddles and window stay in registers;
 //   * S_alpha = |sum_k conj(Z_k) H_k / sqrt(S_k)|^2 / sum_k |H_k|^2 / S_k over
-//     the window's bins inside the row (FP32 products and sums within each
-//     row of 16 lanes, FP64 across rows), 0 when the central bin rint(f T)
-//     is outside the row;
+//     the window's bins inside the row (FP32 products, FP32 tree sums across
+//     the wave, the ratio in FP64), 0 when the central bin rint(f T) is
+//     outside the row;
 //   * S = sum of S_alpha over valid segments, FP64, stored FP32.
 #include <hip/hip_runtime.h>
 
@@ -52,6 +52,11 @@ static_assert(CH_MAX_P < CH_M / 2, "window within the FFT's unaliased bins");
 // LDS slot of FFT element i: one float2 of padding after every four keeps
 // each pass's writes and reads within two-way bank conflicts.
 constexpr int lds_slot(int i) { return i + (i >> 2); }
+// Raw buffer resources (stride 0): word 3 as the gfx9 family takes it; a
+// load at or past num_records bytes returns zero.
+constexpr int CH_RSRC_WORD3 = 0x00020000;
+constexpr unsigned CH_OUTSIDE = 0x80000000u;
+constexpr int CH_MAX_BINS = 1 << 27;   // byte offsets of bins and of CH_OUTSIDE + 8 k0 stay below 2^32
 constexpr int CH_LDS = lds_slot(CH_M - 1) + 1;
 
 struct ChirpParams {
@@ -87,24 +92,47 @@ __device__ __forceinline__ void lds_wave_sync() {
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 }
 
-template <int CTRL>
+template <int CTRL, int ROWS = 0xF>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
 
-// Sum over the wave: FP32 within each row of 16 lanes (quad swaps, then the
-// half-row and row mirrors), FP64 over the four row sums.
-__device__ __forceinline__ double wave_total(float v) {
+// Sum over the wave, FP32, as a tree: quad swaps, the half-row and row
+// mirrors (every lane then holds its row of 16), then rows 0 + 1 and 2 + 3
+// by the row-15 broadcast and all four by the row-31 broadcast, which lands
+// in the last row; the result is read from lane 63.
+__device__ __forceinline__ float wave_total(float v) {
   v += dpp<0xB1>(v);                   // quad_perm [1, 0, 3, 2]
   v += dpp<0x4E>(v);                   // quad_perm [2, 3, 0, 1]
   v += dpp<0x141>(v);                  // row_half_mirror
-  v += dpp<0x140>(v);                  // row_mirror: every lane holds its row's sum
-  const int b = __float_as_int(v);
-  const double r0 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 0));
-  const double r1 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 16));
-  const double r2 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 32));
-  const double r3 = (double)__int_as_float(__builtin_amdgcn_readlane(b, 48));
-  return (r0 + r1) + (r2 + r3);
+  v += dpp<0x140>(v);                  // row_mirror
+  v += dpp<0x142, 0xA>(v);             // row_bcast15 into rows 1 and 3 (rows 0 and 2 add zero)
+  v += dpp<0x143, 0xC>(v);             // row_bcast31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// sin(pi x) and cos(pi x) for finite x of moderate size (|2x| < 2^31): x is
+// reduced to r = x - n/2, |r| <= 1/4, exactly; t = pi r; Taylor polynomials
+// of degree 9 (sine) and 8 (cosine) in t leave a truncation below 2e-9 on
+// |t| <= pi/4; the quadrant n mod 4 swaps and negates.  Absolute error about
+// 1.3 units of 2^-24 in FP32.
+__device__ __forceinline__ void sincospi_reduced(float x, float *sn, float *cs) {
+  const float n = __builtin_rintf(2.0f * x);
+  const float t = fmaf(n, -0.5f, x) * 3.14159265358979f;
+  const float z = t * t;
+  float ps = fmaf(z, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = fmaf(z, ps, 1.0f / 120.0f);
+  ps = fmaf(z, ps, -1.0f / 6.0f);
+  const float s = fmaf(t * z, ps, t);
+  float pc = fmaf(z, 1.0f / 40320.0f, -1.0f / 720.0f);
+  pc = fmaf(z, pc, 1.0f / 24.0f);
+  pc = fmaf(z, pc, -0.5f);
+  const float c = fmaf(z, pc, 1.0f);
+  const int q = (int)n;
+  const bool swap = (q & 1) != 0;
+  const float a = swap ? c : s, b = swap ? s : c;
+  *sn = __int_as_float(__float_as_int(a) ^ ((q & 2) << 30));
+  *cs = __int_as_float(__float_as_int(b) ^ (((q + 1) & 2) << 30));
 }
 
 __device__ __forceinline__ float readlane_f(float v, int l) {
@@ -162,18 +190,26 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
   const int wr0 = lds_slot(4 * lane);                                   // + r: element 4 lane + r
   const int wr1 = lds_slot(16 * (lane >> 2) + (lane & 3));              // + 5 r: element ... + 4 r
   const int wr2 = lds_slot(64 * (lane >> 4) + (lane & 15));             // + 20 r: element ... + 16 r
-  int jo[4];
-  bool in_win[4];
+  // byte offsets, from the central bin, of the bins of the lane's outputs
+  // (output lane + 64 r is bin offset jo); outside the window they carry
+  // 2^31, which keeps every such load past the end of its buffer
+  unsigned zoff[4], ioff[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    jo[r] = lane + 64 * r - (r >= 2 ? CH_M : 0);                        // output lane + 64 r is bin offset jo
-    in_win[r] = jo[r] >= -p.p_half && jo[r] <= p.p_half;
+    const int jo = lane + 64 * r - (r >= 2 ? CH_M : 0);
+    const bool in_win = jo >= -p.p_half && jo <= p.p_half;
+    zoff[r] = in_win ? (unsigned)jo * 8u : CH_OUTSIDE;
+    ioff[r] = in_win ? (unsigned)jo * 4u : CH_OUTSIDE;
   }
+  // bins outside the row read as zero: raw buffer loads past num_records
+  const __amdgpu_buffer_rsrc_t isq_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc((void *)p.isq, (short)0, p.n_bins * 4, CH_RSRC_WORD3);
 
   const double T = p.t_sft;
   const int n = p.n_seg, K = p.K;
   const float *cj = p.coeffs + (size_t)j * K;
-  double total = 0.0;
+  double num = 0.0, den = 0.0;          // this lane's slot: one segment of the chunk
+  double total = 0.0;                   // this lane's share of S
   for (int base = 0; base < n; base += 64) {
     // ---- this chunk's segment parameters, one segment per lane ----
     const int a = base + lane;
@@ -225,14 +261,15 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       todo &= todo - 1;
       const int k0 = __builtin_amdgcn_readlane(k0v, l);
       const float d0 = readlane_f(d0v, l), beta = readlane_f(bv, l);
-      const float2 *zrow = p.Z + (size_t)(base + l) * p.pitch;
+      const __amdgpu_buffer_rsrc_t zrow = __builtin_amdgcn_make_buffer_rsrc(
+          (void *)(p.Z + (size_t)(base + l) * p.pitch), (short)0, p.n_bins * 8, CH_RSRC_WORD3);
       // samples (lane holds m = lane + 64 q) and the first butterfly
       float2 v[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const float ph = uq[q] * fmaf(beta, uq[q], 2.0f * d0);         // phase / pi
         float sn, cs;
-        sincospif(ph, &sn, &cs);
+        sincospi_reduced(ph, &sn, &cs);
         v[q] = make_float2(win[q] * cs, win[q] * sn);
       }
       butterfly4(v);
@@ -262,25 +299,32 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
 #pragma unroll
       for (int r = 1; r < 4; ++r) v[r] = cmul(v[r], tw[2][r - 1]);
       butterfly4(v);
-      // window sums over the lane's bins k0 + jo[r]
+      // window sums over the lane's bins (outside the window or the row: zero)
       float nr = 0.0f, ni = 0.0f, dn = 0.0f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int k = k0 + jo[r];
-        if (in_win[r] && (unsigned)k < (unsigned)p.n_bins) {
-          const float s = p.isq[k];
-          const float2 z = zrow[k];
-          const float hr = v[r].x * s, hi = v[r].y * s;
-          nr = fmaf(z.x, hr, fmaf(z.y, hi, nr));                        // conj(z) * h
-          ni = fmaf(z.x, hi, fmaf(-z.y, hr, ni));
-          dn = fmaf(hr, hr, fmaf(hi, hi, dn));
-        }
+        const float s = __builtin_amdgcn_raw_buffer_load_b32(isq_rsrc, (unsigned)k0 * 4u + ioff[r], 0, 0);
+        const auto zb = __builtin_amdgcn_raw_buffer_load_b64(zrow, (unsigned)k0 * 8u + zoff[r], 0, 0);
+        const float zx = __uint_as_float(zb[0]), zy = __uint_as_float(zb[1]);
+        const float hr = v[r].x * s, hi = v[r].y * s;
+        nr = fmaf(zx, hr, fmaf(zy, hi, nr));                            // conj(z) * h
+        ni = fmaf(zx, hi, fmaf(-zy, hr, ni));
+        dn = fmaf(hr, hr, fmaf(hi, hi, dn));
       }
-      const double NR = wave_total(nr), NI = wave_total(ni), DN = wave_total(dn);
-      if (DN > 0.0) total += (NR * NR + NI * NI) / DN;
+      const double NR = wave_total(nr), NI = wave_total(ni), DN = wave_total(dn);   // FP32 sums
+      if (lane == l) {
+        num = NR * NR + NI * NI;
+        den = DN;
+      }
       asm volatile("" ::: "memory");   // the next segment's first writes follow this segment's last reads
     }
+    if (use && den > 0.0) total += num / den;
+    num = 0.0;
+    den = 0.0;
   }
+  // S over the lanes' shares, FP64
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) total += __shfl_xor(total, off, 64);
   if (lane == 0) p.stat[j] = (float)total;
 }
 
@@ -322,6 +366,7 @@ int check_chirp(const emri_power *pw, int32_t K, int64_t n_tmpl, int32_t top_k, 
     return fail(EMRI_EINVAL, "bad SFT geometry");
   if (!std::isfinite(pw->t_sft) || !(pw->t_sft > 0.0)) return fail(EMRI_EINVAL, "t_sft must be finite and > 0");
   if (pw->n_seg > CH_MAX_SEG) return fail(EMRI_EUNSUPPORTED, "at most %d segments", CH_MAX_SEG);
+  if (pw->n_bins > CH_MAX_BINS) return fail(EMRI_EUNSUPPORTED, "at most %d bins", CH_MAX_BINS);
   if (K < 0 || K > EMRI_MAX_K) return fail(EMRI_EINVAL, "K = %d outside [0, %d]", K, EMRI_MAX_K);
   if (n_tmpl < 0 || n_tmpl > INT32_MAX) return fail(EMRI_EINVAL, "n_tmpl out of range");
   if (top_k < 0 || top_k > EMRI_MAX_TOPK) return fail(EMRI_EINVAL, "top_k out of range");
