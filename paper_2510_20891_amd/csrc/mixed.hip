@@ -429,6 +429,10 @@ __global__ __launch_bounds__(SCORE_THREADS) void score_mixed_batched_kernel(cons
   }
 }
 
+// Templates per lane.  Above K = 13 four spill (the pieces take 6 KG VGPRs
+// per template, and two waves per SIMD leave 256), but three, which fit, are
+// slower: one-year K = 16, 1e8 templates, 17.2 ms with three against 15.9 ms
+// with four, the rows being staged once per 1536 rather than 2048 templates.
 constexpr int mixed_tpl(int K) { return K <= 4 ? 8 : (K <= 8 ? 6 : 4); }
 
 template <typename Kern>
