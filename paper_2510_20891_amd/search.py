@@ -11,9 +11,9 @@ of the same search on noise-only data, and the best normalised value over
 durations is the detection statistic.
 
 Here every duration is one chain and all chains advance together: each
-generation is one trial launch, one batched scoring launch over every chain
-and one selection launch (``SearchPlan.generation``), and a run of
-generations is captured into one HIP graph and replayed.  This module only
+generation is two launches over every chain (``SearchPlan.generation``: one
+that forms, projects and scores every walker's trial, one that selects), and
+a run of generations is captured into one HIP graph and replayed.  This module only
 builds the chain views (pointer offsets into one spectrogram and one basis)
 and launches; the arithmetic is in the library's kernels.  Random numbers
 (seed candidates, initial frequencies, partners, weights) are inputs.
