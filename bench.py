@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak (packed FMA)
+FP32_VECTOR_PEAK_TFLOPS = 157.3       # MI355X published FP32 vector peak
+FP64_VECTOR_PEAK_TFLOPS = 78.6        # MI355X published FP64 vector peak
 
 
 def progress(msg: str) -> None:
@@ -320,8 +321,14 @@ def harmonics_form(st, n: int = 10_000_000, reps: int = 5) -> dict:
     """The multi-harmonic statistic (Sec. IV) on the one-year workload: 1e7
     templates, K = 8, top-256, FP32 power, harmonics at ratios 1, 1/2, 3/2 of
     the searched track (the m = 2, 1, 3 harmonics of a circular orbit), beside
-    the single-harmonic call on the same batch.  Algorithmic bytes count one
-    gathered power element per template, segment and harmonic."""
+    the single-harmonic call on the same batch.
+
+    Roofline: the harmonics' power lookups are LDS gathers from rows already
+    staged for the searched harmonic, so counted as HBM bytes they exceed the
+    HBM peak (reported as lookup_GBps); the form is priced instead on its FP64
+    arithmetic, 2 (K + H) flops per template and segment (K fused
+    multiply-adds for the position, one per harmonic that scales and rounds),
+    against the FP64 vector peak."""
     import torch
     import paper_2510_20891_amd as emri
     dev = torch.device("cuda:0")
@@ -341,7 +348,9 @@ def harmonics_form(st, n: int = 10_000_000, reps: int = 5) -> dict:
                                                          workspace=ws), reps)
     ms_1 = _event_ms(lambda: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, out=out, workspace=ws), reps)
     H, n_seg = len(ratios), spec.n_seg
-    b_eff = n * (4 * K + 4) + n * n_seg * H * 4 + n_seg * spec.n_bins * 4
+    b_look = n * (4 * K + 4) + n * n_seg * H * 4 + n_seg * spec.n_bins * 4
+    flops = 2 * (K + H) * n * n_seg
+    achieved = flops / (ms_h0 * 1e-3) / 1e12
     progress(f"harmonics form: {ms_h:.2f} ms for {H} harmonics, {ms_1:.2f} ms for one")
     return {"workload": f"one-year stream, {n} templates x {n_seg} segments, K = {K}, harmonics {list(ratios)}, "
                         f"top-{top_k}, FP32 power, FP64 positions",
@@ -349,9 +358,10 @@ def harmonics_form(st, n: int = 10_000_000, reps: int = 5) -> dict:
             "evals_per_s": n * n_seg / (ms_h * 1e-3),
             "harmonic_evals_per_s": n * n_seg * H / (ms_h * 1e-3),
             "cost_vs_single": ms_h / ms_1,
-            "roofline": {"bound": "hbm", "achieved": b_eff / (ms_h0 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                         "unit": "GB/s", "frac": b_eff / (ms_h0 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "algorithmic_bytes_per_launch": b_eff}}
+            "lookup_GBps": b_look / (ms_h0 * 1e-3) / 1e9,
+            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "algorithmic_flops_per_eval": 2 * (K + H),
+                         "algorithmic_flops_per_launch": flops}}
 
 
 CHIRP_M = 256                       # template FFT length of the chirp kernel
