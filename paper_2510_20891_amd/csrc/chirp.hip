@@ -263,6 +263,17 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       const float d0 = readlane_f(d0v, l), beta = readlane_f(bv, l);
       const __amdgpu_buffer_rsrc_t zrow = __builtin_amdgcn_make_buffer_rsrc(
           (void *)(p.Z + (size_t)(base + l) * p.pitch), (short)0, p.n_bins * 8, CH_RSRC_WORD3);
+      // the window's data and weights depend on k0 only: their loads go out
+      // first and land while the samples and the FFT are computed
+      float sw[4];
+      float2 zw[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sw[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(isq_rsrc, (unsigned)k0 * 4u + ioff[r], 0, 0));
+        const auto zb = __builtin_amdgcn_raw_buffer_load_b64(zrow, (unsigned)k0 * 8u + zoff[r], 0, 0);
+        zw[r] = make_float2(__uint_as_float(zb[0]), __uint_as_float(zb[1]));
+      }
+      __builtin_amdgcn_sched_barrier(0);
       // samples (lane holds m = lane + 64 q) and the first butterfly
       float2 v[4];
 #pragma unroll
@@ -303,9 +314,8 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       float nr = 0.0f, ni = 0.0f, dn = 0.0f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float s = __builtin_amdgcn_raw_buffer_load_b32(isq_rsrc, (unsigned)k0 * 4u + ioff[r], 0, 0);
-        const auto zb = __builtin_amdgcn_raw_buffer_load_b64(zrow, (unsigned)k0 * 8u + zoff[r], 0, 0);
-        const float zx = __uint_as_float(zb[0]), zy = __uint_as_float(zb[1]);
+        const float s = sw[r];
+        const float zx = zw[r].x, zy = zw[r].y;
         const float hr = v[r].x * s, hi = v[r].y * s;
         nr = fmaf(zx, hr, fmaf(zy, hi, nr));                            // conj(z) * h
         ni = fmaf(zx, hi, fmaf(-zy, hr, ni));

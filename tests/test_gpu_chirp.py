@@ -130,6 +130,32 @@ def test_chirp_half_widths_and_cuts(gpu_lib, p_half):
         assert np.allclose(got, want, rtol=1e-5, atol=0)
 
 
+@pytest.mark.parametrize("p_half", [37, 100])
+def test_chirp_psd_weighting(gpu_lib, p_half):
+    """A PSD that changes from bin to bin (uniform in [1, 40]) over twelve
+    segments holding a noisy linear chirp: the 1/S weighting of every window
+    bin matters here (a kernel that ignored it, or read the weights wrongly,
+    would be off by 2-46 %)."""
+    import torch
+    emri = gpu_lib
+    g = np.random.default_rng(21)
+    n_sft, dt, n_seg, K = 2048, 5.0, 12, 3
+    n_bins = n_sft // 2 + 1
+    T = n_sft * dt
+    psd = g.uniform(1.0, 40.0, n_bins)
+    x = g.standard_normal(n_sft * n_seg) * 3.0
+    t = np.arange(x.size) * dt
+    x += 0.8 * np.cos(2 * np.pi * (300.3 / T) * t + np.pi * (2.0 / T ** 2) * t * t)
+    spec = emri.build_sfts(_t(x), dt, n_sft, _t(psd), dtype="c32")
+    torch.cuda.synchronize()
+    tm = (np.arange(n_seg) + 0.5) * T
+    f0 = (300.3 + 2.0 * tm / T) / T
+    v = (tm - tm.mean()) / T / n_seg
+    U = np.stack([np.ones(n_seg), v, v * v], axis=1) * (4.0 / T)
+    C = g.uniform(-2, 2, (40, K)).astype(np.float32)
+    _compare(emri, {"psd": psd}, spec, f0, U, C, 5, p_half=p_half, f_min=-np.inf, fdot_min=-np.inf)
+
+
 def test_chirp_one_year_sampled(gpu_lib):
     """The one-year complex SFTs (192 segments x 8193 bins), K = 8, 2e5 templates in
     the box, P = 100: 8 sampled templates and the top-10 against the oracle."""
