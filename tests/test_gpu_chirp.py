@@ -156,6 +156,29 @@ def test_chirp_psd_weighting(gpu_lib, p_half):
     _compare(emri, {"psd": psd}, spec, f0, U, C, 5, p_half=p_half, f_min=-np.inf, fdot_min=-np.inf)
 
 
+@pytest.mark.parametrize("n_seg,K", [(1, 2), (2, 2), (3, 1), (3, 0), (64, 2), (65, 3), (130, 2)])
+def test_chirp_segment_counts_and_K(gpu_lib, n_seg, K):
+    """One and two segments (the derivatives' special cases), three, a full
+    64-segment chunk, a ragged second chunk, K = 0 (every template is f0);
+    P = 10, cut-offs off; against the oracle; an empty batch is accepted."""
+    import torch
+    emri = gpu_lib
+    g = np.random.default_rng(500 + n_seg + K)
+    n_sft, dt = 512, 2.0
+    T = n_sft * dt
+    psd = g.uniform(5.0, 15.0, n_sft // 2 + 1)
+    x = g.standard_normal(n_sft * n_seg)
+    spec = emri.build_sfts(_t(x), dt, n_sft, _t(psd), dtype="c32")
+    torch.cuda.synchronize()
+    f0 = g.uniform(60.0, 190.0, n_seg) / T
+    U = g.standard_normal((n_seg, K)) * (3.0 / T)
+    C = g.uniform(-2, 2, (33, K)).astype(np.float32)
+    _compare(emri, {"psd": psd}, spec, f0, U, C, 4, p_half=10, f_min=-np.inf, fdot_min=-np.inf)
+    res = emri.score_tracks_chirp(spec, _t(psd), _t(f0), _t(U), _t(C[:0]), 0, p_half=10)
+    torch.cuda.synchronize()
+    assert res["stat"].numel() == 0
+
+
 def test_chirp_one_year_sampled(gpu_lib):
     """The one-year complex SFTs (192 segments x 8193 bins), K = 8, 2e5 templates in
     the box, P = 100: 8 sampled templates and the top-10 against the oracle."""
