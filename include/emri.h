@@ -395,6 +395,21 @@ int search_generation(const emri_search_plan *plan, const int32_t *r1, const int
                       int32_t *accepted, void *hip_stream);
 
 /*
+ * search_generations -- n_gen >= 0 generations of Eq. (11), each exactly as
+ * search_generation (same trials, statistics and acceptance, bit for bit):
+ * generation g takes r1, r2 and F from row g of device arrays of n_gen x
+ * (total walkers of the plan) entries.  Two generations at a time run as one
+ * launch each, reading one copy of the population and writing the other (the
+ * second copy lives in the plan's workspace), so that every trial sees the
+ * population of the previous generation; an odd last generation runs as
+ * search_generation does.  When the call's work is done the population is in
+ * the chains' coeffs and stat.  Launches only: it may be captured into a HIP
+ * graph.
+ */
+int search_generations(const emri_search_plan *plan, int32_t n_gen, const int32_t *r1, const int32_t *r2,
+                       const double *F, void *hip_stream);
+
+/*
  * search_best -- per chain, the best walker by (-S, index) (NaN ranks last):
  * best_stat FP32[n_chains], best_idx INT32[n_chains]; and, if best_norm is
  * given (FP64[n_chains]), its statistic normalised by the chain's noise-only

@@ -107,6 +107,7 @@ SIGNATURES = {
     "search_plan": (ctypes.c_int, [ctypes.POINTER(_Chain), _i32, _i32, ctypes.POINTER(_BatchOpts), _vp, _sz,
                                    ctypes.POINTER(_SearchPlan), _vp]),
     "search_generation": (ctypes.c_int, [ctypes.POINTER(_SearchPlan), _vp, _vp, _vp, _vp, _vp]),
+    "search_generations": (ctypes.c_int, [ctypes.POINTER(_SearchPlan), _i32, _vp, _vp, _vp, _vp]),
     "search_best": (ctypes.c_int, [ctypes.POINTER(_SearchPlan), _vp, _vp, _vp, _vp, _vp, _vp]),
     "search_noise_moments": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "emri_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -620,6 +621,21 @@ class SearchPlan:
                 raise ValueError("accepted needs one entry per walker")
         _check("search_generation", load().search_generation(ctypes.byref(self._plan), _ptr(r1), _ptr(r2), _ptr(F),
                                                              _ptr(accepted), _stream(stream)))
+
+    def generations(self, r1, r2, F, stream=None) -> None:
+        """len(r1) generations (r1, r2: int32 and F: float64 device tensors of
+        shape (n_gen, walkers)), two at a time in one launch each; the result
+        is that of as many generation() calls, bit for bit."""
+        import torch
+        _require_cuda(r1, torch.int32, "r1")
+        _require_cuda(r2, torch.int32, "r2")
+        _require_cuda(F, torch.float64, "F")
+        n_gen = int(r1.shape[0]) if r1.dim() == 2 else 0
+        for t in (r1, r2, F):
+            if t.dim() != 2 or int(t.shape[0]) != n_gen or int(t.shape[1]) != self.n_walkers or not t.is_contiguous():
+                raise ValueError("r1, r2 and F must be contiguous (n_gen, walkers) tensors")
+        _check("search_generations", load().search_generations(ctypes.byref(self._plan), n_gen, _ptr(r1), _ptr(r2),
+                                                               _ptr(F), _stream(stream)))
 
     def best(self, noise_mean=None, noise_std=None, stream=None) -> dict:
         """Per chain: best statistic and walker index, and the normalised statistic if noise moments are given."""

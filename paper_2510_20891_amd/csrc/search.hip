@@ -3,8 +3,10 @@
 // at once (a chain is one population against one spectrogram and basis; the
 // progressive-duration search runs one chain per observed duration).
 //
-// One generation is two launches, both reading device tables written by
-// search_plan, so a generation (or many) can be captured into a HIP graph:
+// One generation is two launches (search_generation), or, for a pair of
+// generations, one launch each (search_generations, with a second copy of
+// the population in the workspace), all reading device tables written by
+// search_plan, so generations can be captured into a HIP graph:
 //   1. de_trial_score_kernel: per walker (eight lanes each), the trial track
 //      f_trial = f + F (f_r1 - f_r2) is formed segment by segment in FP64
 //      (f = f0 + U c), projected back onto the basis with its pseudo-inverse,
@@ -47,6 +49,7 @@ struct ChainDesc {
   const double *f0, *U, *box_lo, *box_hi;
   const double *pinvt;             // pinv(U) transposed: n_seg x K (workspace)
   float *coeffs, *stat;            // the walkers (updated in place)
+  float *coeffs_b, *stat_b;        // second copy of the population (workspace), for fused generations
   float *trial, *trial_stat;       // this generation's trials (workspace)
   const void *power;               // spectrogram rows (FP32 or FP16)
   double t_sft;
@@ -66,6 +69,7 @@ struct SearchPlanData {
   int32_t max_seg;
   int32_t dtype;
   const ChainDesc *chains;
+  int64_t total_walkers;
 };
 static_assert(sizeof(SearchPlanData) <= sizeof(emri_search_plan), "search plan does not fit");
 
@@ -144,20 +148,27 @@ __global__ __launch_bounds__(kSearchThreads) void de_select_kernel(const ChainDe
   if (accepted) accepted[ch.offset + i] = take ? 1 : 0;
 }
 
-// One generation's trials, formed and scored in one launch (the population
-// is only read; de_select_kernel writes it afterwards).  Eight lanes work on
-// one walker: lane s takes segments s, s + 8, s + 16, ...; the projection's
-// partial sums and the statistic's partial sums are combined across the
-// lanes with shuffles in a fixed order.  The trial's coefficients are rounded
-// to FP32 (the walkers' representation) before its positions are evaluated
-// in FP64 as in score_tracks, x = f0 T + sum_k c_k (U T)[alpha, k], rounded to
-// the nearest bin (half to even); the power is gathered from the spectrogram
-// in place (a population of a few hundred walkers reads too few elements of a
-// row to pay for staging rows in LDS), eight gathers in flight per lane.  Each
-// lane sums its segments in FP32 runs of 8 and in FP64 across runs and lanes.
+// One generation's trials.  Eight lanes work on one walker: lane s takes
+// segments s, s + 8, s + 16, ...; the projection's partial sums and the
+// statistic's partial sums are combined across the lanes with shuffles in a
+// fixed order.  The trial's coefficients are rounded to FP32 (the walkers'
+// representation) before its positions are evaluated in FP64 as in
+// score_tracks, x = f0 T + sum_k c_k (U T)[alpha, k], rounded to the nearest
+// bin (half to even); the power is gathered from the spectrogram in place (a
+// population of a few hundred walkers reads too few elements of a row to pay
+// for staging rows in LDS), up to 32 gathers per lane in flight at once.
+// Each lane sums its segments in FP32 runs of 8 and in FP64 across runs and
+// lanes.
+//
+// de_trial_score_kernel writes the trials and de_select_kernel selects
+// afterwards (the population is only read meanwhile); de_generation_kernel
+// does both in one launch, reading one copy of the population and writing
+// the other (DIR 0: the chain's arrays to the workspace copy, DIR 1 back),
+// so that every trial still sees the population of the previous generation.
 constexpr int kLanesPerWalker = 8;      // measured: 16 lanes and 512 threads 33 us, 8 and 256 27 us
 constexpr int kTrialThreads = 256;
 constexpr int kWalkersPerBlock = kTrialThreads / kLanesPerWalker;
+constexpr int kGatherRun = 32;          // gathers per lane in flight (one run covers 256 segments)
 
 template <typename PT>
 __device__ __forceinline__ float power_at(const void *p, size_t at);
@@ -170,31 +181,20 @@ __device__ __forceinline__ float power_at<__half>(const void *p, size_t at) {
   return (float)__builtin_bit_cast(_Float16, reinterpret_cast<const unsigned short *>(p)[at]);
 }
 
-template <int K, bool STAGE, typename PT>
-__global__ __launch_bounds__(kTrialThreads) void de_trial_score_kernel(const ChainDesc *__restrict__ chains,
-                                                                        const int32_t *__restrict__ r1,
-                                                                        const int32_t *__restrict__ r2,
-                                                                        const double *__restrict__ F) {
-  extern __shared__ double stage_rows[];
-  const ChainDesc ch = load_uniform(chains + blockIdx.y);
-  if ((int)(blockIdx.x * kWalkersPerBlock) >= ch.n_walkers) return;    // whole workgroup idle
-  const BasisRows B = basis_rows<STAGE, kTrialThreads>(ch, K, stage_rows);
-  const int sub = (int)(threadIdx.x & (kLanesPerWalker - 1));
-  const int i_raw = blockIdx.x * kWalkersPerBlock + (int)(threadIdx.x / kLanesPerWalker);
-  const bool live = i_raw < ch.n_walkers;
-  const int i = live ? i_raw : 0;                  // idle lanes compute walker 0 and store nothing
-  const int64_t gi = ch.offset + i;
-  const int a = r1[gi], b = r2[gi];
-  const bool valid = a >= 0 && a < ch.n_walkers && b >= 0 && b < ch.n_walkers && a != i && b != i && a != b;
+// Trial of walker i of a chain whose population is pop (FP32, n_walkers x K):
+// its FP32 coefficients ct (NaN when the partners are invalid) and its
+// statistic (identical in every lane of the walker; -inf when invalid).
+template <int K, typename PT>
+__device__ __forceinline__ float trial_of(const ChainDesc &ch, const BasisRows &B, const float *__restrict__ pop,
+                                          int i, int sub, int a, int b, bool valid, double w, float (&ct)[K]) {
   double ci[K], ca[K], cb[K], out[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    ci[k] = (double)ch.coeffs[(size_t)i * K + k];
-    ca[k] = valid ? (double)ch.coeffs[(size_t)a * K + k] : ci[k];
-    cb[k] = valid ? (double)ch.coeffs[(size_t)b * K + k] : ci[k];
+    ci[k] = (double)pop[(size_t)i * K + k];
+    ca[k] = valid ? (double)pop[(size_t)a * K + k] : ci[k];
+    cb[k] = valid ? (double)pop[(size_t)b * K + k] : ci[k];
     out[k] = 0.0;
   }
-  const double w = valid ? F[gi] : 0.0;
   for (int alpha = sub; alpha < ch.n_seg; alpha += kLanesPerWalker) {
     const double *Ua = B.U + (size_t)alpha * B.stride;
     const double fi = track_at<K>(B.f0, Ua, ci, alpha);
@@ -205,7 +205,6 @@ __global__ __launch_bounds__(kTrialThreads) void de_trial_score_kernel(const Cha
 #pragma unroll
     for (int k = 0; k < K; ++k) out[k] = __builtin_fma(Pa[k], d, out[k]);
   }
-  float ct[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double v = out[k];
@@ -213,45 +212,127 @@ __global__ __launch_bounds__(kTrialThreads) void de_trial_score_kernel(const Cha
     for (int off = kLanesPerWalker / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kLanesPerWalker);
     ct[k] = valid ? (float)v : __builtin_nanf("");
   }
-  // the trial's statistic
-  // eight segments per lane at a time: their bins first, then their eight
-  // gathers in flight together, then one FP32 run summed into FP64
+  // the trial's statistic: a run's bins first, then its gathers in flight
+  // together, then FP32 runs of 8 segments summed into FP64
   const double T = ch.t_sft;
   double sum = 0.0;
-  constexpr int RUN = 8;
-  for (int alpha0 = sub; alpha0 < ch.n_seg; alpha0 += RUN * kLanesPerWalker) {
-    size_t at[RUN];
-    bool in[RUN];
+  for (int base = 0; base < ch.n_seg; base += kGatherRun * kLanesPerWalker) {
+    // slots u < n_run hold a segment for some lane of the walker (wave-uniform)
+    const int left = (ch.n_seg - base + kLanesPerWalker - 1) / kLanesPerWalker;
+    const int n_run = left < kGatherRun ? left : kGatherRun;
+    unsigned at[kGatherRun];
+    bool in[kGatherRun];
+    float v[kGatherRun];
 #pragma unroll
-    for (int u = 0; u < RUN; ++u) {
-      const int alpha = alpha0 + u * kLanesPerWalker;
-      const int ar = alpha < ch.n_seg ? alpha : sub;
-      const double *Ua = B.U + (size_t)ar * B.stride;
-      double x = B.f0[ar] * T;
+    for (int u = 0; u < kGatherRun; ++u) {
+      in[u] = false;
+      v[u] = 0.0f;
+      if (u < n_run) {
+        const int alpha = base + sub + u * kLanesPerWalker;
+        const int ar = alpha < ch.n_seg ? alpha : sub;
+        const double *Ua = B.U + (size_t)ar * B.stride;
+        double x = B.f0[ar] * T;
 #pragma unroll
-      for (int k = 0; k < K; ++k) x = __builtin_fma((double)ct[k], Ua[k] * T, x);
-      const bool finite = __builtin_fabs(x) < 67108864.0;                // 2^26 bins; NaN fails
-      const int bin = finite ? (int)__builtin_rint(x) : -1;
-      in[u] = alpha < ch.n_seg && finite && bin >= ch.k_min && bin <= ch.k_max;
-      at[u] = (size_t)ar * ch.pitch + (in[u] ? bin : ch.k_min);
+        for (int k = 0; k < K; ++k) x = __builtin_fma((double)ct[k], Ua[k] * T, x);
+        const bool finite = __builtin_fabs(x) < 67108864.0;              // 2^26 bins; NaN fails
+        const int bin = finite ? (int)__builtin_rint(x) : -1;
+        in[u] = alpha < ch.n_seg && finite && bin >= ch.k_min && bin <= ch.k_max;
+        at[u] = (unsigned)ar * (unsigned)ch.pitch + (unsigned)(in[u] ? bin : ch.k_min);
+      }
     }
-    float v[RUN];
 #pragma unroll
-    for (int u = 0; u < RUN; ++u) v[u] = power_at<PT>(ch.power, at[u]);
-    float acc = 0.0f;
+    for (int u = 0; u < kGatherRun; ++u)
+      if (u < n_run) v[u] = power_at<PT>(ch.power, at[u]);
 #pragma unroll
-    for (int u = 0; u < RUN; ++u) acc += in[u] ? v[u] : 0.0f;
-    sum += (double)acc;
+    for (int r = 0; r < kGatherRun; r += 8) {
+      if (r < n_run) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int u = r; u < r + 8; ++u) acc += in[u] ? v[u] : 0.0f;
+        sum += (double)acc;
+      }
+    }
   }
 #pragma unroll
   for (int off = kLanesPerWalker / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, kLanesPerWalker);
-  if (live) {
-    for (int k = sub; k < K; k += kLanesPerWalker) {
+  return valid ? (float)sum : -__builtin_inff();
+}
+
+struct WalkerSlot {
+  int i, sub, a, b;
+  bool live, valid;
+  double w;
+};
+
+__device__ __forceinline__ WalkerSlot walker_slot(const ChainDesc &ch, const int32_t *r1, const int32_t *r2,
+                                                  const double *F) {
+  WalkerSlot ws;
+  ws.sub = (int)(threadIdx.x & (kLanesPerWalker - 1));
+  const int i_raw = blockIdx.x * kWalkersPerBlock + (int)(threadIdx.x / kLanesPerWalker);
+  ws.live = i_raw < ch.n_walkers;
+  ws.i = ws.live ? i_raw : 0;                      // idle lanes compute walker 0 and store nothing
+  const int64_t gi = ch.offset + ws.i;
+  ws.a = r1[gi];
+  ws.b = r2[gi];
+  ws.valid = ws.a >= 0 && ws.a < ch.n_walkers && ws.b >= 0 && ws.b < ch.n_walkers && ws.a != ws.i &&
+             ws.b != ws.i && ws.a != ws.b;
+  ws.w = ws.valid ? F[gi] : 0.0;
+  return ws;
+}
+
+template <int K, bool STAGE, typename PT>
+__global__ __launch_bounds__(kTrialThreads) void de_trial_score_kernel(const ChainDesc *__restrict__ chains,
+                                                                        const int32_t *__restrict__ r1,
+                                                                        const int32_t *__restrict__ r2,
+                                                                        const double *__restrict__ F) {
+  extern __shared__ double stage_rows[];
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  if ((int)(blockIdx.x * kWalkersPerBlock) >= ch.n_walkers) return;    // whole workgroup idle
+  const BasisRows B = basis_rows<STAGE, kTrialThreads>(ch, K, stage_rows);
+  const WalkerSlot ws = walker_slot(ch, r1, r2, F);
+  float ct[K];
+  const float ts = trial_of<K, PT>(ch, B, ch.coeffs, ws.i, ws.sub, ws.a, ws.b, ws.valid, ws.w, ct);
+  if (ws.live) {
+    for (int k = ws.sub; k < K; k += kLanesPerWalker) {
 #pragma unroll
       for (int q = 0; q < K; ++q)
-        if (q == k) ch.trial[(size_t)i * K + k] = ct[q];
+        if (q == k) ch.trial[(size_t)ws.i * K + k] = ct[q];
     }
-    if (sub == 0) ch.trial_stat[i] = valid ? (float)sum : -__builtin_inff();
+    if (ws.sub == 0) ch.trial_stat[ws.i] = ts;
+  }
+}
+
+template <int K, bool STAGE, typename PT>
+__global__ __launch_bounds__(kTrialThreads) void de_generation_kernel(const ChainDesc *__restrict__ chains,
+                                                                       const int32_t *__restrict__ r1,
+                                                                       const int32_t *__restrict__ r2,
+                                                                       const double *__restrict__ F, int dir) {
+  extern __shared__ double stage_rows[];
+  const ChainDesc ch = load_uniform(chains + blockIdx.y);
+  if ((int)(blockIdx.x * kWalkersPerBlock) >= ch.n_walkers) return;    // whole workgroup idle
+  const BasisRows B = basis_rows<STAGE, kTrialThreads>(ch, K, stage_rows);
+  const float *pop = dir == 0 ? ch.coeffs : ch.coeffs_b;
+  const float *pstat = dir == 0 ? ch.stat : ch.stat_b;
+  float *dst = dir == 0 ? ch.coeffs_b : ch.coeffs;
+  float *dstat = dir == 0 ? ch.stat_b : ch.stat;
+  const WalkerSlot ws = walker_slot(ch, r1, r2, F);
+  float ct[K];
+  const float ts = trial_of<K, PT>(ch, B, pop, ws.i, ws.sub, ws.a, ws.b, ws.valid, ws.w, ct);
+  bool inside = true;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double v = (double)ct[k];
+    inside &= v >= ch.box_lo[k] && v <= ch.box_hi[k];                  // NaN: outside
+  }
+  const float old = pstat[ws.i];
+  const bool take = inside && ts > old;
+  if (ws.live) {
+    for (int k = ws.sub; k < K; k += kLanesPerWalker) {
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        if (q == k) dst[(size_t)ws.i * K + k] = take ? ct[q] : pop[(size_t)ws.i * K + k];
+    }
+    if (ws.sub == 0) dstat[ws.i] = take ? ts : old;
   }
 }
 
@@ -405,6 +486,29 @@ hipError_t launch_trial_score(int K, int dtype, int max_seg, dim3 grid, hipStrea
 }
 
 template <int... Ks>
+hipError_t launch_generation(int K, int dtype, int max_seg, dim3 grid, hipStream_t stream, const ChainDesc *chains,
+                             const int32_t *r1, const int32_t *r2, const double *F, int dir,
+                             std::integer_sequence<int, Ks...>) {
+  hipError_t err = hipErrorInvalidValue;
+  const size_t lds = stage_bytes(max_seg, K);
+  auto one = [&](auto kc, auto pt) {
+    constexpr int KK = decltype(kc)::value;
+    using PT = typename decltype(pt)::type;
+    auto kern = lds ? de_generation_kernel<KK, true, PT> : de_generation_kernel<KK, false, PT>;
+    err = hipFuncSetAttribute(reinterpret_cast<const void *>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (err != hipSuccess) return;
+    hipLaunchKernelGGL(kern, grid, dim3(kTrialThreads), lds, stream, chains, r1, r2, F, dir);
+    err = hipGetLastError();
+  };
+  if (dtype == EMRI_F32)
+    ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}, type_tag<float>{}), true) : false) || ...);
+  else
+    ((K == Ks + 1 ? (one(std::integral_constant<int, Ks + 1>{}, type_tag<__half>{}), true) : false) || ...);
+  return err;
+}
+
+template <int... Ks>
 hipError_t launch_seed_move(int K, int max_seg, dim3 grid, hipStream_t stream, const ChainDesc *chains,
                             const float *draws, const double *f_init, int n_draw, float *cand, int64_t cand_stride,
                             std::integer_sequence<int, Ks...>) {
@@ -440,7 +544,7 @@ int check_chain(const emri_chain &c, int i) {
 
 struct SearchLayout {
   size_t chains, trials, total;
-  std::vector<size_t> trial_off, tstat_off, pinv_off;
+  std::vector<size_t> trial_off, tstat_off, pinv_off, popb_off, statb_off;
 };
 
 SearchLayout search_layout(const emri_chain *chains, int n, int K) {
@@ -457,6 +561,8 @@ SearchLayout search_layout(const emri_chain *chains, int n, int K) {
     L.trial_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers * K));
     L.tstat_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers));
     L.pinv_off.push_back(take(sizeof(double) * (size_t)chains[i].power.n_seg * K));
+    L.popb_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers * K));
+    L.statb_off.push_back(take(sizeof(float) * (size_t)chains[i].n_walkers));
   }
   L.total = off;
   return L;
@@ -486,6 +592,8 @@ int check_chain_power(const emri_chain &c, int i, int dtype) {
   const int k_max = c.k_max < 0 ? pw.n_bins - 1 : c.k_max;
   if (c.k_min < 0 || k_max > pw.n_bins - 1 || c.k_min > k_max)
     return fail(EMRI_EINVAL, "chain %d: bin range outside the row", i);
+  if ((uint64_t)pw.n_seg * (uint64_t)pw.row_pitch >= (1ull << 32))
+    return fail(EMRI_EUNSUPPORTED, "chain %d: n_seg x row_pitch must stay below 2^32 elements", i);
   return EMRI_OK;
 }
 
@@ -562,6 +670,8 @@ extern "C" int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K
     d.coeffs = chains[i].coeffs;
     d.stat = chains[i].stat;
     d.pinvt = reinterpret_cast<const double *>(ws + L.pinv_off[i]);
+    d.coeffs_b = reinterpret_cast<float *>(ws + L.popb_off[i]);
+    d.stat_b = reinterpret_cast<float *>(ws + L.statb_off[i]);
     d.trial = reinterpret_cast<float *>(ws + L.trial_off[i]);
     d.trial_stat = reinterpret_cast<float *>(ws + L.tstat_off[i]);
     d.power = chains[i].power.data;
@@ -590,6 +700,7 @@ extern "C" int search_plan(const emri_chain *chains, int32_t n_chains, int32_t K
   pd.max_seg = max_seg;
   pd.dtype = dtype;
   pd.chains = reinterpret_cast<const ChainDesc *>(ws + L.chains);
+  pd.total_walkers = offset;
   std::memset(plan, 0, sizeof *plan);
   std::memcpy(plan, &pd, sizeof pd);
   return EMRI_OK;
@@ -617,6 +728,39 @@ extern "C" int search_generation(const emri_search_plan *plan, const int32_t *r1
                      pd.chains, pd.K, accepted);
   err = hipGetLastError();
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "select launch: %s", hipGetErrorString(err));
+  return EMRI_OK;
+}
+
+extern "C" int search_generations(const emri_search_plan *plan, int32_t n_gen, const int32_t *r1, const int32_t *r2,
+                                  const double *F, void *hip_stream) {
+  clear_error();
+  SearchPlanData pd;
+  int st = plan_data(plan, &pd);
+  if (st) return st;
+  if (n_gen < 0) return fail(EMRI_EINVAL, "n_gen %d < 0", n_gen);
+  if (n_gen > 0 && (!r1 || !r2 || !F)) return fail(EMRI_EINVAL, "r1, r2 and F are required");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const dim3 sgrid((unsigned)((pd.max_walkers + kWalkersPerBlock - 1) / kWalkersPerBlock), (unsigned)pd.n_chains);
+  const int64_t T = pd.total_walkers;
+  int g = 0;
+  for (; g + 1 < n_gen; g += 2) {       // a pair: to the workspace copy and back, one launch each
+    for (int dir = 0; dir < 2; ++dir) {
+      const int64_t o = (int64_t)(g + dir) * T;
+      hipError_t err = launch_generation(pd.K, pd.dtype, pd.max_seg, sgrid, stream, pd.chains, r1 + o, r2 + o, F + o,
+                                         dir, AllK{});
+      if (err != hipSuccess) return fail(EMRI_EDEVICE, "generation launch: %s", hipGetErrorString(err));
+    }
+  }
+  if (g < n_gen) {                      // an odd last generation: trials, then selection in place
+    const int64_t o = (int64_t)g * T;
+    hipError_t err = launch_trial_score(pd.K, pd.dtype, pd.max_seg, sgrid, stream, pd.chains, r1 + o, r2 + o, F + o,
+                                        AllK{});
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "trial launch: %s", hipGetErrorString(err));
+    hipLaunchKernelGGL(de_select_kernel, walker_grid(pd.max_walkers, pd.n_chains), dim3(kSearchThreads), 0, stream,
+                       pd.chains, pd.K, nullptr);
+    err = hipGetLastError();
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "select launch: %s", hipGetErrorString(err));
+  }
   return EMRI_OK;
 }
 

@@ -10,10 +10,11 @@ duration's best statistic is normalised by the mean and standard deviation
 of the same search on noise-only data, and the best normalised value over
 durations is the detection statistic.
 
-Here every duration is one chain and all chains advance together: each
-generation is two launches over every chain (``SearchPlan.generation``: one
-that forms, projects and scores every walker's trial, one that selects), and
-a run of generations is captured into one HIP graph and replayed.  This module only
+Here every duration is one chain and all chains advance together: a pair of
+generations is two launches over every chain (``SearchPlan.generations``:
+each forms, projects and scores every walker's trial and selects, reading
+one copy of the population and writing the other), and a run of generations
+is captured into one HIP graph and replayed.  This module only
 builds the chain views (pointer offsets into one spectrogram and one basis)
 and launches; the arithmetic is in the library's kernels.  Random numbers
 (seed candidates, initial frequencies, partners, weights) are inputs.
@@ -84,8 +85,7 @@ def prepare(chains: list, K: int, draws, f_init, r1, r2, F, precision: str = "pl
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        for g in range(int(r1.shape[0])):
-            plan.generation(r1[g], r2[g], F[g])
+        plan.generations(r1, r2, F)
     return SearchRun(list(chains), plan, graph, int(r1.shape[0]))
 
 

@@ -274,6 +274,8 @@ def test_search_sizes_and_plan_arguments():
     assert lib.search_seed_workspace_size(arr, 2, 8, 20, ctypes.byref(nb)) == -1     # 40 walkers of 20 draws
     plan = emri._SearchPlan()
     assert lib.search_generation(ctypes.byref(plan), FAKE, FAKE, FAKE, None, None) == -1   # not a plan
+    assert lib.search_generations(ctypes.byref(plan), 2, FAKE, FAKE, FAKE, None) == -1     # not a plan
+    assert lib.search_generations(None, 2, FAKE, FAKE, FAKE, None) == -1
     assert lib.search_plan(arr, 2, 8, None, FAKE + 16, 1 << 20, ctypes.byref(plan), None) == -1   # alignment
     assert lib.search_plan(arr, 2, 8, None, FAKE, 64, ctypes.byref(plan), None) == -3          # too small
 

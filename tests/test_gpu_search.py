@@ -210,6 +210,54 @@ def test_graph_of_generations_replays_to_eager(world):
         torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("G", [1, 2, 5, 6])
+def test_fused_generations_equal_single_generations(world, G):
+    """search_generations (pairs of generations in one launch each, through a
+    second copy of the population) gives the walkers and statistics of G
+    search_generation calls bit for bit, eagerly and replayed from a graph;
+    an odd G ends with one generation run the single way."""
+    import torch
+    emri, chains = world["emri"], world["chains"]
+    emri.search_seed(chains, K, _t(world["draws"]), _t(world["finit"]))
+    torch.cuda.synchronize()
+    start = [(ch.coeffs.clone(), ch.stat.clone()) for ch in chains]
+    draws = []
+    for gen in range(G):
+        d = [_gen_draws(c, 300 + gen) for c in range(len(chains))]
+        draws.append(tuple(_t(np.concatenate([x[i] for x in d])) for i in range(3)))
+    stacked = tuple(torch.stack([dr[i] for dr in draws]).contiguous() for i in range(3))
+    plan = emri.SearchPlan(chains, K)
+
+    def reset():
+        for ch, (C, S) in zip(chains, start):
+            ch.coeffs.copy_(C)
+            ch.stat.copy_(S)
+        torch.cuda.synchronize()
+
+    for gen in range(G):
+        plan.generation(*draws[gen])
+    torch.cuda.synchronize()
+    single = [(ch.coeffs.clone(), ch.stat.clone()) for ch in chains]
+    assert any(not torch.equal(a[0], b[0]) for a, b in zip(single, start))
+    reset()
+    plan.generations(*stacked)
+    torch.cuda.synchronize()
+    for ch, (C, S) in zip(chains, single):
+        assert torch.equal(ch.coeffs, C) and torch.equal(ch.stat, S)
+    graph = torch.cuda.CUDAGraph()
+    reset()
+    with torch.cuda.graph(graph):
+        plan.generations(*stacked)
+    for rep in range(2):
+        reset()
+        graph.replay()
+        torch.cuda.synchronize()
+        for ch, (C, S) in zip(chains, single):
+            assert torch.equal(ch.coeffs, C) and torch.equal(ch.stat, S), rep
+        plan.best()
+        torch.cuda.synchronize()
+
+
 def test_invalid_partners_keep_the_walker(world):
     import torch
     emri, chains = world["emri"], world["chains"]
