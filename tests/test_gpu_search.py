@@ -161,6 +161,68 @@ def test_generations_match_oracle(world):
     assert n_acc > 0
 
 
+def test_fp16_power_generations(world):
+    """FP16 spectrogram rows: one generation against the oracle on the same
+    FP16 power (acceptance, trials and statistics as above), and fused pairs
+    equal to single generations bit for bit."""
+    import torch
+    emri, t, lo, hi = world["emri"], world["t"], world["lo"], world["hi"]
+    st = synth.stream_config1(stream=0)
+    f0, U, sv, lo_, hi_ = oracle.build_basis(st["tracks"], K)
+    spec = emri.build_sfts(_t(st["x"]), st["dt"], st["n_sft"], _t(st["psd"]), dtype="f16")
+    torch.cuda.synchronize()
+    P16 = _np(spec.power()).astype(np.float64)
+    N = spec.n_seg
+    chains, host, states = [], [], []
+    for c, n in enumerate((192, 63)):
+        sub = emri.Spectrogram(spec.data[:n], spec.n_bins, spec.t_sft)
+        chains.append(emri.Chain(sub, _t(f0[N - n:]), _t(U[N - n:]), _t(lo), _t(hi),
+                                 torch.zeros((N_WALK, K), dtype=torch.float32, device="cuda"),
+                                 torch.zeros(N_WALK, dtype=torch.float32, device="cuda")))
+        h = dict(P=P16[:n], f0=f0[N - n:], U=U[N - n:])
+        host.append(h)
+        d = world["draws"][c * N_DRAW:(c + 1) * N_DRAW]
+        fi = world["finit"][c * N_DRAW:(c + 1) * N_DRAW]
+        C, S, _ = osr.seed_population(h["P"], h["f0"], h["U"], d, fi, t, N_WALK)
+        states.append((C, S))
+    plan = emri.SearchPlan(chains, K)
+    draws = [_gen_draws(c, 40) for c in range(len(chains))]
+    r1, r2, F = (_t(np.concatenate([d[i] for d in draws])) for i in range(3))
+    _set_state(chains, states)
+    acc = torch.full((len(chains) * N_WALK,), -1, dtype=torch.int32, device="cuda")
+    plan.generation(r1, r2, F, acc)
+    torch.cuda.synchronize()
+    acc = _np(acc).reshape(len(chains), N_WALK)
+    n_acc = 0
+    for c, (ch, h) in enumerate(zip(chains, host)):
+        C0, S0 = states[c]
+        S0f = S0.astype(np.float32).astype(np.float64)
+        o = osr.de_generation(h["P"], h["f0"], h["U"], lo, hi, C0, S0f, *draws[c], t)
+        near = (oracle.near_tie_mask(_positions(h, o["trial"], t)).any(axis=1)
+                | oracle.near_tie_mask(_positions(h, C0, t)).any(axis=1))
+        close = np.abs(o["trial_stat"] - S0f) <= 2e-5 * np.abs(S0f)
+        amb = near | (close & o["in_prior"])
+        assert np.array_equal(acc[c][~amb].astype(bool), o["accepted"][~amb]), c
+        took = (acc[c] == 1) & ~amb
+        rel = np.abs(_np(ch.stat)[took] - o["trial_stat"][took]) / np.abs(o["trial_stat"][took])
+        assert rel.size == 0 or rel.max() <= 1e-5
+        n_acc += int(acc[c].sum())
+    assert n_acc > 0
+    # fused pair == two single generations, bit for bit
+    more = [[_gen_draws(c, 41 + g) for c in range(len(chains))] for g in range(2)]
+    per_gen = [tuple(_t(np.concatenate([d[i] for d in dg])) for i in range(3)) for dg in more]
+    _set_state(chains, states)
+    for g in range(2):
+        plan.generation(*per_gen[g])
+    torch.cuda.synchronize()
+    single = [(ch.coeffs.clone(), ch.stat.clone()) for ch in chains]
+    _set_state(chains, states)
+    plan.generations(*(torch.stack([pg[i] for pg in per_gen]).contiguous() for i in range(3)))
+    torch.cuda.synchronize()
+    for ch, (C, S) in zip(chains, single):
+        assert torch.equal(ch.coeffs, C) and torch.equal(ch.stat, S)
+
+
 def test_graph_of_generations_replays_to_eager(world):
     import torch
     emri, chains = world["emri"], world["chains"]
