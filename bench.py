@@ -265,11 +265,14 @@ def batched_form(n_streams: int = 64, reps: int = 5) -> dict:
     return out
 
 
-def serving_form(seconds: float = 32.0, warmup: float = 2.0, precision: str = "plain") -> dict:
+def serving_form(seconds: float = 32.0, warmup: float = 2.0, precision: str = "plain",
+                 sweep_rates=(8000.0, 32000.0), sweep_seconds: float = 6.0) -> dict:
     """Config 4: 16 resident one-year FP16 spectrograms with a shared K = 8 basis;
     Poisson arrivals at 2000 requests/s of floor(logU[256, 65536]) templates
     against a uniform random stream, top-32 each; latency over the arrivals
-    after the first ``warmup`` seconds."""
+    after the first ``warmup`` seconds.  Then a load sweep: the same server at
+    higher arrival rates for ``sweep_seconds`` each (first second excluded),
+    where requests overlap and batches grow, up to the device's throughput."""
     import torch
     import paper_2510_20891_amd as emri
     from paper_2510_20891_amd.serving import GpuExecutor, Request, Server
@@ -309,12 +312,28 @@ def serving_form(seconds: float = 32.0, warmup: float = 2.0, precision: str = "p
         torch.cuda.synchronize()
         same &= bool(np.array_equal(ref["topk_idx"].cpu().numpy(), r.topk_idx)
                      and np.array_equal(ref["topk_val"].cpu().numpy(), r.topk_val))
+    sweep = []
+    for rate in sweep_rates:
+        rq = [Request(r["rid"], r["stream"], pool[r["offset"]:r["offset"] + r["n"]], r["top_k"], r["t"])
+              for r in synth.serving_requests(n_streams, rate, sweep_seconds, cfg=40 + int(rate) % 97,
+                                              pool_size=pool.shape[0])]
+        sv = Server(ex, K, hbm_budget=budget, max_batch_templates=max_t, max_requests=max_r, slots=slots,
+                    seg_counts=segs)
+        sv.run(rq)
+        ss = sv.stats(rq, warmup_s=1.0)
+        sweep.append({"offered_req_per_s": rate, "requests": ss.n_requests, "latency_ms": ss.latency_ms,
+                      "throughput_req_per_s": ss.n_requests / ss.wall_s,
+                      "throughput_evals_per_s": ss.evals / ss.wall_s, "batches": ss.batches,
+                      "mean_batch_requests": ss.mean_batch_requests, "max_queue": ss.max_queue})
+        progress(f"serving sweep {rate:g} req/s: p50 {ss.latency_ms['p50']:.2f} ms, p99 {ss.latency_ms['p99']:.2f} ms, "
+                 f"{ss.mean_batch_requests:.1f} requests per batch")
     return {"workload": f"16 resident one-year FP16 spectrograms, Poisson 2000 req/s for {seconds:g} s "
                         f"(first {warmup:g} s excluded), logU[256, 65536] templates, top-32, precision {precision}",
             "requests": st.n_requests, "latency_ms": st.latency_ms,
             "throughput_evals_per_s": st.evals / st.wall_s, "throughput_req_per_s": st.n_requests / st.wall_s,
             "batches": st.batches, "mean_batch_requests": st.mean_batch_requests, "max_queue": st.max_queue,
-            "slots": slots, "hbm_budget_bytes": budget, "same_as_standalone_24_sampled": same}
+            "slots": slots, "hbm_budget_bytes": budget, "same_as_standalone_24_sampled": same,
+            "load_sweep": sweep}
 
 
 def harmonics_form(st, n: int = 10_000_000, reps: int = 5) -> dict:
