@@ -266,7 +266,7 @@ def batched_form(n_streams: int = 64, reps: int = 5) -> dict:
 
 
 def serving_form(seconds: float = 32.0, warmup: float = 2.0, precision: str = "plain",
-                 sweep_rates=(8000.0, 32000.0), sweep_seconds: float = 6.0) -> dict:
+                 sweep_rates=(8000.0, 32000.0, 128000.0), sweep_seconds: float = 6.0) -> dict:
     """Config 4: 16 resident one-year FP16 spectrograms with a shared K = 8 basis;
     Poisson arrivals at 2000 requests/s of floor(logU[256, 65536]) templates
     against a uniform random stream, top-32 each; latency over the arrivals

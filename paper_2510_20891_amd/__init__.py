@@ -518,6 +518,30 @@ class BatchPlan:
         _check("score_batched_run", load().score_batched_run(ctypes.byref(self._plan), _stream(stream)))
 
 
+class RawBatchPlan:
+    """A batched launch planned from a filled ``_Problem`` array (raw device
+    pointers, e.g. sub-buffers of a caller's preallocated tensors): the fast
+    path for a serving loop that plans a batch per launch.  The caller keeps
+    every buffer the array points to alive while the plan is used."""
+
+    def __init__(self, arr, n: int, K: int, precision: str = "plain", workspace=None, device=None, stream=None):
+        lib = load()
+        self.K = int(K)
+        self._arr = arr
+        nbytes = ctypes.c_size_t(0)
+        _check("score_batched_workspace_size", lib.score_batched_workspace_size(arr, int(n), self.K,
+                                                                                ctypes.byref(nbytes)))
+        self._ws = workspace or Workspace()
+        ws_ptr, ws_len = self._ws.get(int(nbytes.value), device, stream)
+        self.opts = _BatchOpts(0, 0, _PRECISIONS[precision])
+        self._plan = _Plan()
+        _check("score_batched_plan", lib.score_batched_plan(arr, int(n), self.K, ctypes.byref(self.opts), ws_ptr,
+                                                            ws_len, ctypes.byref(self._plan), _stream(stream)))
+
+    def run(self, stream=None) -> None:
+        _check("score_batched_run", load().score_batched_run(ctypes.byref(self._plan), _stream(stream)))
+
+
 @dataclass
 class Chain:
     """One search population (device tensors): ``coeffs`` (n_walkers, K) float32 and

@@ -85,26 +85,47 @@ class GpuExecutor:
         self.events = [None] * slots
         self.batches = [None] * slots
         self.plans = [None] * slots
+        # the per-slot problem tables, filled per batch with raw pointers into
+        # the slot's buffers (same sub-buffers and 16-byte alignment as slices)
+        from . import _Problem
+        self.tables = [(_Problem * int(max_requests))() for _ in range(slots)]
+        self.powers = [s_._struct() for s_ in specs]
+        self.f0_ptr = [int(t.data_ptr()) for t in f0s]
+        self.U_ptr = [int(t.data_ptr()) for t in Us]
+        self.device = dev
 
     def launch(self, slot: int, reqs: list) -> None:
         import torch
-        from . import BatchPlan, Problem
+        from . import RawBatchPlan
         st = self.streams[slot]
-        offs, off = [], 0
+        K = self.K
         hc = self.h_coeffs[slot].numpy()
-        for r in reqs:
-            offs.append(off)
-            hc[off:off + r.n] = r.coeffs
-            off += (r.n + 3) // 4 * 4
-        problems = []
+        tab = self.tables[slot]
+        c0 = int(self.d_coeffs[slot].data_ptr())
+        s0 = int(self.d_stat[slot].data_ptr())
+        v0 = int(self.d_val[slot].data_ptr())
+        i0 = int(self.d_idx[slot].data_ptr())
+        off = 0
+        for i, r in enumerate(reqs):
+            n = r.n
+            hc[off:off + n] = r.coeffs
+            a = tab[i]
+            a.power = self.powers[r.stream]
+            a.f0 = self.f0_ptr[r.stream]
+            a.U = self.U_ptr[r.stream] if K else None
+            a.coeffs = c0 + 4 * K * off if K and n else None
+            a.n_tmpl = n
+            a.top_k = r.top_k
+            a.k_min = 0
+            a.k_max = -1
+            a.stat = s0 + 4 * off if n else None
+            a.topk_val = v0 + 4 * self.top_k * i if r.top_k else None
+            a.topk_idx = i0 + 8 * self.top_k * i if r.top_k else None
+            off += (n + 3) // 4 * 4
         with torch.cuda.stream(st):
             self.d_coeffs[slot][:off].copy_(self.h_coeffs[slot][:off], non_blocking=True)
-            for i, (r, o) in enumerate(zip(reqs, offs)):
-                problems.append(Problem(self.specs[r.stream], self.f0s[r.stream], self.Us[r.stream],
-                                        self.d_coeffs[slot][o:o + r.n], top_k=r.top_k,
-                                        stat=self.d_stat[slot][o:o + r.n],
-                                        topk_val=self.d_val[slot][i, :r.top_k], topk_idx=self.d_idx[slot][i, :r.top_k]))
-            plan = BatchPlan(problems, self.K, precision=self.precision, workspace=self.ws[slot], stream=st)
+            plan = RawBatchPlan(tab, len(reqs), K, precision=self.precision, workspace=self.ws[slot],
+                                device=self.device, stream=st)
             plan.run(st)
             nr = len(reqs)
             self.h_val[slot][:nr].copy_(self.d_val[slot][:nr], non_blocking=True)
