@@ -230,8 +230,8 @@ int score_tracks_harmonics(const emri_power *power, const double *f0, const doub
  * f[alpha] = f0[alpha] + sum_k c_k U[alpha, k] (FP64), fdot and fddot its
  * second-order finite differences over the segment grid (central inside,
  * one-sided fdot at the ends, the neighbour's fddot at the ends), k0 =
- * rint(f T) inside the row (else the segment contributes nothing) and, over
- * the bins k = k0 - P..k0 + P inside the row,
+ * rint(f T) inside the row and fdot T^2 finite in FP32 (else the segment
+ * contributes nothing) and, over the bins k = k0 - P..k0 + P inside the row,
  *     H_k      = R(f T - k, fdot T^2) (up to a factor common to all k),
  *     R(d, b)  = int_{-1/2}^{1/2} cos^2(pi u) exp(2 pi i d u + i pi b u^2) du
  *                (the SFT of the Hann-windowed unit linear chirp, Eqs. (4)-(5)),

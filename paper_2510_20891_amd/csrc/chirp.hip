@@ -249,9 +249,10 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       if (valid && __builtin_fabs(x) < 1e9) {                           // else far outside any row
         const double k0d = __builtin_rint(x);
         k0v = (int)k0d;
-        use = k0v >= 0 && k0v < p.n_bins;                               // central bin outside the row: no contribution
         d0v = (float)(x - k0d);
         bv = (float)(fd * T * T);
+        // central bin outside the row, or b beyond FP32: no contribution
+        use = k0v >= 0 && k0v < p.n_bins && __builtin_fabsf(bv) <= 3.4028234663852886e38f;
       }
     }
     uint64_t todo = __ballot(use);
