@@ -1,12 +1,17 @@
 /*
  * emri.h -- C ABI of the MI355X (gfx950) library for the semi-coherent
- * single-harmonic EMRI track search (arXiv 2510.20891).
+ * EMRI track search (arXiv 2510.20891).
  *
- * The library builds a PSD-normalised SFT power spectrogram from a time series,
- * builds an SVD basis of frequency tracks, and scores very large batches of
- * basis-coefficient vectors against the spectrogram: every track is rebuilt at
- * every segment midpoint, the power in its nearest frequency bin is looked up,
- * the lookups are summed over segments and the best tracks are kept (top-k).
+ * The library builds a PSD-normalised SFT power spectrogram (or the whitened
+ * complex SFTs) from a time series, builds an SVD basis of frequency tracks,
+ * and scores very large batches of basis-coefficient vectors against the
+ * spectrogram: every track is rebuilt at every segment midpoint, the power in
+ * its nearest frequency bin is looked up, the lookups are summed over
+ * segments and the best tracks are kept (top-k).  Beside this nearest-bin
+ * statistic it evaluates the 201-bin linear-chirp statistic
+ * (score_tracks_chirp), a multi-harmonic statistic (score_tracks_harmonics),
+ * many independent streams in one launch (score_batched_*), and the
+ * population search over coefficients (search_*).
  *
  * Conventions shared by every call
  *   - Plain C types only.  Pointers documented as "device" point to GPU memory
@@ -14,9 +19,9 @@
  *   - Every buffer, including the scoring workspace, is allocated by the caller.
  *     The library never allocates device memory.  Device calls only enqueue
  *     work on `hip_stream` (a hipStream_t; NULL is the default stream) and
- *     return without synchronising, except score_batched_plan (a set-up call
- *     that waits for its own table copies).  Outputs are valid once the caller
- *     has synchronised that stream.
+ *     return without synchronising, except the set-up calls score_batched_plan,
+ *     search_seed and search_plan, which wait for their own table copies.
+ *     Outputs are valid once the caller has synchronised that stream.
  *   - Every call returns an emri_status.  Arguments are validated before any HIP
  *     call; on failure nothing is enqueued and emri_last_error() describes why.
  *     Nothing is thrown or aborted across the boundary.
