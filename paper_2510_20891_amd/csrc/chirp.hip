@@ -20,7 +20,13 @@
 //     common factor; the integrand vanishes smoothly at both ends, so the
 //     sum converges like the integral's aliased tail: relative error below
 //     4e-7 for |b| <= 60 and P = 100), by a four-pass radix-4 Stockham FFT,
-//     FP32: each lane holds the samples m = lane + 64 q, which are the inputs
+//     FP32: each lane holds the samples m = lane + 64 q (q = 0..3); their
+//     phases form a quadratic sequence in q, so the lane evaluates the sample
+//     at q = 0 and the step to q = 1 (two sine/cosine pairs) and takes the
+//     rest by complex products, the step growing by the factor e^{i pi b / 8}
+//     of the segment (evaluated once per segment in the parameter pass;
+//     phase error a few units of 2^-24 of the phases, up to ~1e-5 rad);
+//     these samples are the inputs
 //     of its first butterfly, and keeps the outputs j = lane + 64 q of its
 //     last; the two middle exchanges go through the wave's LDS buffer (padded
 //     against bank conflicts), twiddles and window stay in registers;
@@ -215,7 +221,7 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
     const int a = base + lane;
     bool use = false;
     int k0v = 0;
-    float d0v = 0.0f, bv = 0.0f;
+    float d0v = 0.0f, bv = 0.0f, qsv = 0.0f, qcv = 1.0f;
     if (a < n) {
       auto track = [&](int i) {
         double f = p.f0[i];
@@ -253,6 +259,7 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
         bv = (float)(fd * T * T);
         // central bin outside the row, or b beyond FP32: no contribution
         use = k0v >= 0 && k0v < p.n_bins && __builtin_fabsf(bv) <= 3.4028234663852886e38f;
+        if (use) sincospi_reduced(bv * 0.125f, &qsv, &qcv);                 // e^{i pi b / 8}: second difference of the phase
       }
     }
     uint64_t todo = __ballot(use);
@@ -262,6 +269,7 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       todo &= todo - 1;
       const int k0 = __builtin_amdgcn_readlane(k0v, l);
       const float d0 = readlane_f(d0v, l), beta = readlane_f(bv, l);
+      const float2 Qs = make_float2(readlane_f(qcv, l), readlane_f(qsv, l));
       const __amdgpu_buffer_rsrc_t zrow = __builtin_amdgcn_make_buffer_rsrc(
           (void *)(p.Z + (size_t)(base + l) * p.pitch), (short)0, p.n_bins * 8, CH_RSRC_WORD3);
       // the window's data and weights depend on k0 only: their loads go out
@@ -277,12 +285,23 @@ __global__ __launch_bounds__(CH_THREADS) void chirp_score_kernel(ChirpParams p) 
       __builtin_amdgcn_sched_barrier(0);
       // samples (lane holds m = lane + 64 q) and the first butterfly
       float2 v[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float ph = uq[q] * fmaf(beta, uq[q], 2.0f * d0);         // phase / pi
-        float sn, cs;
+      {
+        // phase / pi at u0 and its first difference to u0 + 1/4; later
+        // differences grow by b / 8, so the samples follow by products
+        const float u0 = uq[0];
+        const float ph = u0 * fmaf(beta, u0, 2.0f * d0);
+        const float dph = fmaf(beta, 2.0f * u0 + 0.25f, 2.0f * d0) * 0.25f;
+        float sn, cs, rs, rc;
         sincospi_reduced(ph, &sn, &cs);
-        v[q] = make_float2(win[q] * cs, win[q] * sn);
+        sincospi_reduced(dph, &rs, &rc);
+        float2 e = make_float2(cs, sn), r = make_float2(rc, rs);
+        v[0] = make_float2(win[0] * e.x, win[0] * e.y);
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          e = cmul(e, r);
+          if (q < 3) r = cmul(r, Qs);
+          v[q] = make_float2(win[q] * e.x, win[q] * e.y);
+        }
       }
       butterfly4(v);
 #pragma unroll

@@ -3,10 +3,12 @@
 Bars (from the arithmetic): complex SFTs within one FP32 rounding of the
 oracle's FP64 values (plus 1e-13 of the row's largest magnitude); the
 statistic within 1e-4 relative per template (the GPU evaluates the template
-as a 256-point FP32 DFT, relative error below 4e-7 of the continuum
-template, and sums in FP32 within lanes: its error on S_alpha is ~1e-6
-typical, larger only where a segment's inner product nearly cancels, which
-carries little weight in the sum); segment validity decided identically.
+as a 256-point FP32 DFT of samples whose phases come from a short product
+recurrence, within ~1e-5 of the continuum template, and sums in FP32 trees:
+its error on S is ~1e-6 typical and up to ~2e-5 over 1e6 one-year
+templates, larger only where a segment's inner product nearly cancels,
+which carries little weight in the sum); segment validity decided
+identically.
 """
 import numpy as np
 import pytest
