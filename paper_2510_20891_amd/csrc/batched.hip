@@ -34,6 +34,7 @@ struct PlanData {
   int64_t topk_blocks;
   int32_t n_items;
   int32_t has_work;
+  int32_t topk_fast;           // some top-k job takes the sampled threshold
 };
 static_assert(sizeof(PlanData) <= sizeof(emri_batch_plan), "plan does not fit");
 
@@ -226,6 +227,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   std::vector<PrepJob> preps(n_problems);
   std::vector<TopkJob> topks;
   int64_t max_topk_n = 0;
+  bool any_fast = false;
   for (int i = 0; i < n_problems; ++i) {
     const emri_problem &pb = problems[i];
     const int k_max = pb.k_max < 0 ? pb.power.n_bins - 1 : pb.k_max;
@@ -268,6 +270,8 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     if (pb.top_k > 0) {
       pj.topk = reinterpret_cast<TopkState *>(ws + L.topk_off[i]);
       topks.push_back(make_topk_job(p.stat, pb.n_tmpl, pb.top_k, pb.topk_val, pb.topk_idx, ws + L.topk_off[i]));
+      topks.back().fast_r = topk_fast_rank(pb.n_tmpl, topks.back().kk);
+      any_fast = any_fast || topks.back().fast_r != 0u;
       max_topk_n = std::max(max_topk_n, pb.n_tmpl);
     }
   }
@@ -343,6 +347,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.topk_blocks = topk_blocks;
   pd.n_items = (int)items.size();
   pd.has_work = items.empty() ? 0 : 1;
+  pd.topk_fast = any_fast ? 1 : 0;
   std::memset(plan, 0, sizeof *plan);
   std::memcpy(plan, &pd, sizeof pd);
   return EMRI_OK;
@@ -363,7 +368,7 @@ extern "C" int score_batched_run(const emri_batch_plan *plan, void *hip_stream) 
     std::memset(&J, 0, sizeof J);
     J.jobs = pd.topk_jobs;
     J.block_job = pd.topk_block_job;
-    err = launch_topk_jobs(J, pd.topk_blocks, pd.max_topk_n, stream);
+    err = launch_topk_jobs(J, pd.topk_blocks, pd.max_topk_n, stream, 0, pd.topk_fast != 0);
   }
   if (err != hipSuccess) return fail(EMRI_EDEVICE, "batched launch: %s", hipGetErrorString(err));
   return EMRI_OK;

@@ -458,9 +458,16 @@ __global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) {
   prep_one(job, false);
 }
 
+// Problem blockIdx.x: workgroup y = 0 computes its constants, the others
+// reset a share of its top-k state each.
 __global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs, int *counter) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;     // work-item counter of the scoring launch
-  prep_one(load_uniform(jobs + blockIdx.x), true);
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;   // work items of the scoring launch
+  const PrepJob job = load_uniform(jobs + blockIdx.x);
+  if (blockIdx.y > 0) {
+    if (job.topk) topk_state_reset(job.topk, blockIdx.y - 1, gridDim.y - 1);
+    return;
+  }
+  prep_one(job, false);
 }
 
 // Templates per lane: as many FMA chains as the 256 VGPRs of two waves per SIMD
@@ -558,7 +565,7 @@ hipError_t launch_score_prep(const PrepJob &job, hipStream_t stream) {
 
 hipError_t launch_score_prep_batched(const PrepJob *jobs, int n_jobs, int *counter, hipStream_t stream) {
   if (n_jobs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(score_prep_batched_kernel, dim3(n_jobs), dim3(256), 0, stream, jobs, counter);
+  hipLaunchKernelGGL(score_prep_batched_kernel, dim3(n_jobs, 1 + PREP_RESET_PARTS), dim3(256), 0, stream, jobs, counter);
   return hipGetLastError();
 }
 

@@ -267,13 +267,14 @@ __device__ __forceinline__ unsigned long long get_candidate(const unsigned long 
 // LDS (leaving the state's zero for the next pass), then the workgroup scans it
 // from the largest digit down (keys) or the smallest up (indices) and fixes
 // the digit that holds the need-th element.  `first`: the first pass of its kind
-// (its prefix starts empty; the first key pass needs kk elements); `decide`:
+// (its prefix starts empty; the first key pass needs kk elements, or
+// first_need if that is not zero); `decide`:
 // the second key pass, which chooses between gathering and the remaining
 // radix passes; `last`: the final key pass, which also sets up the tie passes
 // and the compaction.
 template <bool KEYS, int THREADS>
 __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int width, bool first, bool decide,
-                             bool last) {
+                             bool last, uint32_t first_need = 0u) {
   TopkState *st = job.st;
   const int nb = 1 << width;
   // The whole table, without branches, so that the loads are in flight
@@ -308,7 +309,7 @@ __device__ void select_digit(const TopkJob &job, uint32_t *lh, int shift, int wi
   __syncthreads();
   for (int w = 0; w < wave; ++w) incl += wave_total[w];
   const uint32_t excl = incl - mine;
-  const uint32_t need = KEYS ? (first ? job.kk : st->need) : st->idx_need;
+  const uint32_t need = KEYS ? (first ? (first_need ? first_need : job.kk) : st->need) : st->idx_need;
   if (!(excl < need && need <= incl)) return;
   uint32_t before = excl;
   for (int i = 0; i < per; ++i) {

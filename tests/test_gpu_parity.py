@@ -373,6 +373,40 @@ def test_topk_nan_and_negative(gpu_lib):
     assert list(gpu["topk_idx"]) == [5, 7, 4, 0, 3, 6, 1, 9, 2, 8]
 
 
+def _sampled(n):
+    """Templates the sampled threshold reads: one unit of 64 in every 16 (the
+    statistics past the last whole group of 4 are never sampled)."""
+    i = np.arange(n)
+    return ((i // 64) % 16 == 0) & (i < 4 * (n // 4))
+
+
+@pytest.mark.parametrize("case,k", [("spread", 1), ("spread", 100), ("spread", 256), ("sample_high", 256),
+                                    ("sample_high", 7), ("one_value", 32), ("spread", 257)])
+def test_topk_sampled_threshold(gpu_lib, case, k):
+    """Top-k of 2^16 + 4099 statistics through the validating launch, which
+    does not fuse the first key pass, so that k <= 256 takes the sampled
+    threshold.  `spread`: 8192 distinct values, each held by ~128 templates in
+    random order (the gathered candidates contain the top-k); `sample_high`:
+    every sampled template scores above every other, so at k = 256 fewer than
+    k are gathered and the radix passes decide; `one_value`: all equal, far
+    more than 2048 are gathered and the radix passes decide by index; k = 257
+    never samples.  Each must be exactly the first k by (-S, index)."""
+    n, n_bins, t = (1 << 16) + 4099, 8192, 1.0
+    g = np.random.default_rng(k + 10 * len(case))
+    P = np.sort(g.uniform(1.0, 2.0, (1, n_bins))).astype(np.float32).astype(np.float64)
+    if case == "one_value":
+        P[:] = 1.5
+    c = g.integers(0, n_bins, n)
+    if case == "sample_high":
+        c = np.where(_sampled(n), g.integers(n_bins // 2, n_bins, n), g.integers(0, n_bins // 2, n))
+    gpu = score_gpu(gpu_lib, P, np.zeros(1), np.ones((1, 1)), c.astype(np.float32)[:, None], t, k,
+                    want_near_tie=True)
+    assert np.array_equal(gpu["stat"], P[0, c].astype(np.float32))
+    ov, oi = oracle.topk_order(P[0, c], k)
+    assert np.array_equal(gpu["topk_idx"], oi)
+    assert np.array_equal(gpu["topk_val"], ov.astype(np.float32))
+
+
 def test_one_year_full_size_sampled(gpu_lib):
     """1e7 templates at K = 8 on the one-year stream, in the launch the benchmark
     times: 2e4 sampled templates (plus the top-k and both ends) against the
