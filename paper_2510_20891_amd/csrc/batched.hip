@@ -126,8 +126,8 @@ int resolve_tpl(int K, int requested, int *tpl) {
 int64_t max_items_for(const emri_problem *pbs, int n, int K) {
   int tpl = score_templates_per_lane(K, false);
   if (K == 8 || K == 16) tpl = std::min(tpl, score_templates_per_lane(K, true));
-  if (K >= 1 && K <= MIXED_MAX_K) tpl = std::min(tpl, mixed_templates_per_lane(K));
-  const int64_t tile = (int64_t)tpl * SCORE_THREADS;
+  int64_t tile = (int64_t)tpl * SCORE_THREADS;
+  if (K >= 1 && K <= MIXED_MAX_K) tile = std::min<int64_t>(tile, mixed_tile_templates(K));
   int64_t items = 0;
   for (int i = 0; i < n; ++i) items += (pbs[i].n_tmpl + tile - 1) / tile;
   return items > 0 ? items : 1;
@@ -279,7 +279,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   // work items: two tiles of one problem (a problem's odd last tile alone),
   // in decreasing order of cost (tiles x (segments + 4)), so the launch ends
   // on the cheapest items; workgroups claim them in this order
-  const int64_t tile = tile_of(K, tpl);
+  const int64_t tile = mixed ? mixed_tile_templates(K) : tile_of(K, tpl);
   std::vector<BatchItem> items;
   std::vector<double> cost;
   for (int i = 0; i < n_problems; ++i) {

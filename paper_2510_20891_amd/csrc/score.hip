@@ -435,11 +435,12 @@ __device__ __forceinline__ void prep_one(const PrepJob &job, bool reset_topk) {
       MixedSeg m;
       m.I = 0.0;
       m.phi = 0.0f;
-      m.pad = 0.0f;
+      m.M = 12582912.0f;
       if (a < n_seg) {
         const double v = f0[a] * t_sft;
         m.I = 2.0 * __builtin_rint(0.5 * v);        // even integer nearest v (within 1)
-        m.phi = (float)(v - m.I);                   // exact difference, |phi| <= 1
+        m.phi = (float)(v - m.I);                   // |phi| <= 1
+        if (__builtin_fabs(m.I) < 4194304.0) m.M = (float)(12582912.0 + m.I);   // exact
       }
       ms[a] = m;
     }

@@ -45,14 +45,20 @@ struct ScoreParams {
 };
 
 // Mixed-precision form: per-segment offset f0*T = I + phi with I the even
-// integer nearest f0*T (FP64) and phi in [-1, 1] (FP32).
+// integer nearest f0*T (FP64) and phi in [-1, 1] (FP32); M = 1.5*2^23 + I in
+// FP32 (exact for |I| < 2^22; segments farther out only occur for templates
+// that take the FP64 path, and M is then unused).
 struct MixedSeg {
   double I;
   float phi;
-  float pad;
+  float M;
 };
 
 constexpr int MIXED_MAX_K = 16;
+// The mixed kernel runs 1024-thread workgroups (four waves per SIMD); the
+// first SCORE_WAVES of its waves stage the rows.
+constexpr int MIXED_THREADS = 1024;
+static_assert(MIXED_THREADS % SCORE_THREADS == 0, "the staging waves are a prefix of the workgroup");
 __host__ __device__ constexpr int mixed_groups(int K) { return (K + 3) / 4; }
 // bytes of the BF16 piece table per segment: 3 pieces x groups x 4 values x 2 bytes
 __host__ __device__ constexpr int mixed_row_bytes(int K) { return 3 * mixed_groups(K) * 8; }
@@ -113,6 +119,7 @@ hipError_t launch_score(const ScoreParams &p, int K, int dtype, bool validate, i
 hipError_t launch_score_batched(const BatchLaunch &b, hipStream_t stream);
 // mixed-precision form (BF16-split MFMA contraction, FP64 offset and rounding)
 int mixed_templates_per_lane(int K);
+int mixed_tile_templates(int K);     // templates per tile of the mixed kernel
 hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream);
 hipError_t launch_score_mixed_batched(const BatchLaunch &b, hipStream_t stream);
 // multi-harmonic form (harmonics.hip): 1 <= K <= HARMONICS_MAX_K, 1 <= n_harm <= 4
