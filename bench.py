@@ -133,7 +133,28 @@ def _event_ms(fn, reps: int, stream=None) -> float:
     return statistics.median(out)
 
 
-def precision_form(st, reps: int = 5) -> dict:
+def _event_ms_rotating(fns: dict, reps: int) -> dict:
+    """Median wall time of each fn() by HIP events, the functions timed in
+    rotation (one run of each per round, after one warm-up run each), so that
+    every variant meets the same clock and power state of the chip."""
+    import statistics
+    import torch
+    for fn in fns.values():
+        fn()
+    torch.cuda.synchronize()
+    times = {name: [] for name in fns}
+    for _ in range(reps):
+        for name, fn in fns.items():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            times[name].append(e0.elapsed_time(e1))
+    return {name: statistics.median(t) for name, t in times.items()}
+
+
+def precision_form(st, reps: int = 7) -> dict:
     """Config 2: the one-year stream, 1e8 templates at K = 8 and K = 16, top-100.
     Plain FP32 (the plain path) vs plain FP16 vs mixed FP16; statistic error of
     the mixed form against the FP64 oracle on 2e5 sampled templates; top-100
@@ -161,17 +182,18 @@ def precision_form(st, reps: int = 5) -> dict:
         out = {"stat": torch.empty(n, dtype=torch.float32, device=dev),
                "topk_val": torch.empty(top_k, dtype=torch.float32, device=dev),
                "topk_idx": torch.empty(top_k, dtype=torch.int64, device=dev)}
-        runs = {}
-        for name, spec, prec in (("plain_f32", spec32, "plain"), ("plain_f16", spec16, "plain"),
-                                 ("mixed_f16", spec16, "mixed")):
-            ms = _event_ms(lambda: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, precision=prec, out=out,
-                                                     workspace=ws), reps)
-            runs[name] = {"ms": ms, "evals_per_s": n * spec.n_seg / (ms * 1e-3)}
-            if name == "plain_f16":
-                plain_idx = torch.topk(out["stat"], 2000).indices.cpu().numpy()
-            if name == "mixed_f16":
-                mixed_stat = out["stat"].clone()
-                mixed_top = out["topk_idx"].cpu().numpy()
+        variants = (("plain_f32", spec32, "plain"), ("plain_f16", spec16, "plain"), ("mixed_f16", spec16, "mixed"))
+        call = lambda spec, prec: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, precision=prec, out=out,
+                                                    workspace=ws)
+        times = _event_ms_rotating({name: (lambda spec=spec, prec=prec: call(spec, prec))
+                                    for name, spec, prec in variants}, reps)
+        runs = {name: {"ms": times[name], "evals_per_s": n * spec.n_seg / (times[name] * 1e-3)}
+                for name, spec, prec in variants}
+        call(spec16, "plain")
+        plain_idx = torch.topk(out["stat"], 2000).indices.cpu().numpy()
+        call(spec16, "mixed")
+        mixed_stat = out["stat"].clone()
+        mixed_top = out["topk_idx"].cpu().numpy()
         # statistic error of the mixed form against the oracle (same FP16 power)
         rows = np.random.default_rng(20 + K).integers(0, n, 200_000)
         C_rows = C_d[torch.from_numpy(rows).to(dev)].cpu().numpy()

@@ -49,20 +49,22 @@ constexpr int kPairs = 6;
 constexpr int pair_u(int p) { return p == 0 ? 2 : (p == 1 ? 1 : (p == 2 ? 0 : (p == 3 ? 1 : 0))); }
 constexpr int pair_c(int p) { return p == 0 ? 0 : (p == 1 ? 1 : (p == 2 ? 2 : (p == 3 ? 0 : (p == 4 ? 1 : 0)))); }
 
-__device__ __forceinline__ short4_t pack4(unsigned short a, unsigned short b, unsigned short c, unsigned short d) {
-  short4_t v;
-  v[0] = (short)a;
-  v[1] = (short)b;
-  v[2] = (short)c;
-  v[3] = (short)d;
-  return v;
-}
-
 // The three BF16 pieces of TPL templates' coefficients, KG groups of 4 each.
 template <int KG, int TPL>
 struct Pieces {
   short4_t v[TPL][3][KG];
 };
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float float2_t __attribute__((ext_vector_type(2)));
+
+// Two FP32 values rounded to BF16 (nearest even; one v_cvt_pk_bf16_f32), as
+// one dword (a in the low half), and the FP32 values of those halves.
+__device__ __forceinline__ unsigned bf16_pair(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((float2_t){a, b}, bf16x2_t));
+}
+__device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
 // Load and split the coefficients of this lane's TPL templates of tile t0.
 // Returns true if any of them could place a track at |x| >= 2^21 bins (huge
@@ -94,24 +96,30 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
 #pragma unroll
       for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
     }
-    double b = bnd[0];
+    // the bound in FP32: K + 1 terms, each rounded at most three times
+    // (bound, product, sum), stay within 3 (K + 1) 2^-24 < 1e-5 of the exact
+    // sum, so b < 2^21 (1 - 1e-5) implies the exact bound is below 2^21; then
+    // |I + D| < 2^22 and the FP32 rounding of D + M is exact
+    float b = (float)bnd[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) b += __builtin_fabs((double)cf[k]) * bnd[1 + k];
-    wild |= !(b < 2097152.0);       // then |D| < 2^22 and FP32 rounding of D is exact
+    for (int k = 0; k < K; ++k) b += __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
+    wild |= !(b < 2097152.0f * 0.99999f);
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
-      unsigned short h[3][4];
+      // pieces of coefficients 4g .. 4g+3, two per conversion: each remainder
+      // is exact in FP32, and the last has at most 8 significant bits
+      float r[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float c = cf[4 * g + q];
-        h[0][q] = bf16_rne(c);
-        const float r1 = c - bf16_value(h[0][q]);       // exact
-        h[1][q] = bf16_rne(r1);
-        const float r2 = r1 - bf16_value(h[1][q]);      // exact; at most 8 significant bits
-        h[2][q] = bf16_rne(r2);
+      for (int q = 0; q < 4; ++q) r[q] = cf[4 * g + q];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const unsigned w01 = bf16_pair(r[0], r[1]), w23 = bf16_pair(r[2], r[3]);
+        pc.v[s][a][g] = __builtin_bit_cast(short4_t, (uint2){w01, w23});
+        r[0] -= bf16_lo(w01);
+        r[1] -= bf16_hi(w01);
+        r[2] -= bf16_lo(w23);
+        r[3] -= bf16_hi(w23);
       }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) pc.v[s][a][g] = pack4(h[a][0], h[a][1], h[a][2], h[a][3]);
     }
   }
   return wild;
