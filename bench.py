@@ -160,7 +160,11 @@ def precision_form(st, reps: int = 7) -> dict:
     the mixed form against the FP64 oracle on 2e5 sampled templates; top-100
     overlap against the oracle's exact top-100 (the oracle scores the union of
     the plain and mixed top-2000, which holds the true top-100 because the
-    plain statistic is within 1e-5 of the oracle's)."""
+    plain statistic is within 1e-5 of the oracle's).  mixed_f16_rescore is the
+    mixed form with rescore_top: its top-100 candidates come from the mixed
+    statistic and are re-scored with FP64 positions.  The error is also given
+    over the sampled templates none of whose positions lies within 1e-3 bin of
+    a half-integer (a moved bin needs such a position)."""
     import torch
     import oracle
     import paper_2510_20891_amd as emri
@@ -182,13 +186,17 @@ def precision_form(st, reps: int = 7) -> dict:
         out = {"stat": torch.empty(n, dtype=torch.float32, device=dev),
                "topk_val": torch.empty(top_k, dtype=torch.float32, device=dev),
                "topk_idx": torch.empty(top_k, dtype=torch.int64, device=dev)}
-        variants = (("plain_f32", spec32, "plain"), ("plain_f16", spec16, "plain"), ("mixed_f16", spec16, "mixed"))
-        call = lambda spec, prec: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, precision=prec, out=out,
-                                                    workspace=ws)
-        times = _event_ms_rotating({name: (lambda spec=spec, prec=prec: call(spec, prec))
-                                    for name, spec, prec in variants}, reps)
+        variants = (("plain_f32", spec32, "plain", False), ("plain_f16", spec16, "plain", False),
+                    ("mixed_f16", spec16, "mixed", False), ("mixed_f16_rescore", spec16, "mixed", True))
+        call = lambda spec, prec, rs=False: emri.score_tracks(spec, f0_d, U_d, C_d, top_k, precision=prec,
+                                                              rescore_top=rs, out=out, workspace=ws)
+        times = _event_ms_rotating({name: (lambda spec=spec, prec=prec, rs=rs: call(spec, prec, rs))
+                                    for name, spec, prec, rs in variants}, reps)
         runs = {name: {"ms": times[name], "evals_per_s": n * spec.n_seg / (times[name] * 1e-3)}
-                for name, spec, prec in variants}
+                for name, spec, prec, rs in variants}
+        call(spec16, "mixed", True)
+        resc_top = out["topk_idx"].cpu().numpy()
+        resc_val = out["topk_val"].cpu().numpy()
         call(spec16, "plain")
         plain_idx = torch.topk(out["stat"], 2000).indices.cpu().numpy()
         call(spec16, "mixed")
@@ -199,19 +207,28 @@ def precision_form(st, reps: int = 7) -> dict:
         C_rows = C_d[torch.from_numpy(rows).to(dev)].cpu().numpy()
         o = oracle.score_tracks(P16, f0, U, C_rows, t_sft, 0)
         rel = np.abs(mixed_stat[torch.from_numpy(rows).to(dev)].cpu().numpy() - o["stat"]) / np.abs(o["stat"])
+        x_rows = oracle.track_positions(f0, U, C_rows, t_sft)
+        clear = ~(np.abs(x_rows - np.floor(x_rows) - 0.5) < 1e-3).any(axis=1)
+        del x_rows
         # exact top-100 of the oracle over the candidate union
         mixed_cand = torch.topk(mixed_stat, 2000).indices.cpu().numpy()
         cand = np.unique(np.concatenate([plain_idx, mixed_cand]))
         oc = oracle.score_tracks(P16, f0, U, C_d[torch.from_numpy(cand).to(dev)].cpu().numpy(), t_sft, top_k)
         true_top = set(cand[oc["topk_idx"]].tolist())
+        o_resc = oracle.score_tracks(P16, f0, U, C_d[torch.from_numpy(resc_top).to(dev)].cpu().numpy(), t_sft, 0)
         progress(f"precision form K={K}: mixed {runs['mixed_f16']['ms']:.2f} ms, plain f32 {runs['plain_f32']['ms']:.2f} ms")
         res[f"K{K}"] = {
             **{k: v for k, v in runs.items()},
             "speedup_mixed_vs_plain_f32": runs["plain_f32"]["ms"] / runs["mixed_f16"]["ms"],
             "speedup_mixed_vs_plain_f16": runs["plain_f16"]["ms"] / runs["mixed_f16"]["ms"],
+            "speedup_mixed_rescore_vs_plain_f32": runs["plain_f32"]["ms"] / runs["mixed_f16_rescore"]["ms"],
             "stat_rel_err_vs_oracle": {"p50": float(np.quantile(rel, 0.5)), "p99": float(np.quantile(rel, 0.99)),
-                                       "max": float(rel.max()), "sample": int(rows.size)},
+                                       "max": float(rel.max()), "sample": int(rows.size),
+                                       "max_no_position_within_1e-3_of_half": float(rel[clear].max()),
+                                       "templates_with_such_a_position": float(1.0 - clear.mean())},
             "top100_overlap": len(true_top & set(mixed_top.tolist())),
+            "rescore_top100_overlap": len(true_top & set(resc_top.tolist())),
+            "rescore_top100_max_rel_err_vs_oracle": float(np.max(np.abs(resc_val - o_resc["stat"]) / o_resc["stat"])),
         }
         del C_d, out, mixed_stat
         torch.cuda.empty_cache()

@@ -78,7 +78,9 @@ typedef struct {
   int32_t k_min;          /* lowest bin that contributes (default 0)                      */
   int32_t k_max;          /* highest bin that contributes; < 0 means n_bins - 1 (default) */
   int32_t precision;      /* emri_precision (default EMRI_PLAIN)                          */
-  int32_t reserved[5];    /* must be zero                                                 */
+  int32_t reserved[4];    /* must be zero                                                 */
+  int32_t rescore_top;    /* EMRI_MIXED with top_k > 0: 1 re-scores the leading candidates */
+                          /* with FP64 positions before the top-k (see score_tracks)       */
 } score_opts;
 
 /*
@@ -175,7 +177,17 @@ int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tm
  *   n_near_tie device INT64[1] or NULL: if given, set to the number of
  *              (template, segment) positions within 1e-6 bin of a half-integer.
  *   (bins and n_near_tie select a slower validation kernel.)
- *   opts       NULL or bin range options
+ *   opts       NULL or bin range, precision and re-scoring options
+ *
+ * With precision EMRI_MIXED the positions are FP32 sums (see emri_precision):
+ * a position within the FP32 error (~1e-4 bin at 10^3 bins) of a half-integer
+ * can take the neighbouring bin, so a small share of templates carries one
+ * moved bin.  With rescore_top = 1 (and top_k > 0) the call takes the
+ * kc = min(n_tmpl, max(4 top_k, 64), 4096) best templates of the mixed
+ * statistic, evaluates each again exactly as the plain path does (its FP64
+ * statistic bit for bit, written into stat), and returns the best top_k of
+ * those kc; the plain path ignores rescore_top.
+ *
  *   workspace  device, at least score_tracks_workspace_size() bytes, 256-byte
  *              aligned; its contents on entry are irrelevant.
  */

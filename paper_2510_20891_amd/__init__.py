@@ -45,7 +45,7 @@ class _Power(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("k_min", ctypes.c_int32), ("k_max", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("reserved", ctypes.c_int32 * 4), ("rescore_top", ctypes.c_int32)]
 
 
 _vp, _i32, _i64, _dbl, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
@@ -288,12 +288,14 @@ def default_workspace(device, stream=None) -> Workspace:
 
 def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: bool = True,
                  want_bins: bool = False, want_near_tie: bool = False, k_min: int = 0, k_max: int = -1,
-                 precision: str = "plain", out: dict | None = None, workspace: Workspace | None = None,
-                 stream=None) -> dict:
+                 precision: str = "plain", rescore_top: bool = False, out: dict | None = None,
+                 workspace: Workspace | None = None, stream=None) -> dict:
     """Nearest-bin statistic and top-k of a coefficient batch (device tensors).
 
     f0: (n_seg,) float64;  U: (n_seg, K) float64;  coeffs: (n_tmpl, K) float32.
     precision: "plain" (FP64 contraction) or "mixed" (BF16-split matrix cores, FP64 rounding).
+    rescore_top (mixed, top_k > 0): re-score the leading candidates with FP64
+    positions before the top-k (their stat entries become the plain statistic).
     Returns tensors: ``stat`` (n_tmpl,) float32 if want_stat, ``topk_val`` (top_k,),
     ``topk_idx`` (top_k,) int64, and ``bins`` / ``n_near_tie`` if requested.
     ``out`` may hold preallocated tensors under the same keys.
@@ -323,6 +325,7 @@ def score_tracks(spec: Spectrogram, f0, U, coeffs, top_k: int, *, want_stat: boo
     ws = workspace if workspace is not None else default_workspace(dev, s)
     ws_ptr, ws_len = ws.get(nbytes, dev, s)
     opts = _Opts(int(k_min), int(k_max), _PRECISIONS[precision])
+    opts.rescore_top = int(bool(rescore_top))
     pw = spec._struct()
     _check("score_tracks", load().score_tracks(
         ctypes.byref(pw), _ptr(f0), _ptr(U) if K else None, K, _ptr(coeffs) if K else None, n_tmpl, int(top_k),

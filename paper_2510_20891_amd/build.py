@@ -21,7 +21,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libemri.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["status.cpp", "sft.hip", "score.hip", "mixed.hip", "topk.hip", "api.hip", "batched.hip", "search.hip", "harmonics.hip", "chirp.hip"]
+HIP_SOURCES = ["status.cpp", "sft.hip", "score.hip", "mixed.hip", "topk.hip", "api.hip", "batched.hip", "search.hip", "harmonics.hip", "chirp.hip", "rescore.hip"]
 HOST_SOURCES = ["basis.cpp"]
 
 

@@ -9,6 +9,7 @@
 #include "common.h"
 #include "score_internal.h"
 #include "topk_internal.h"
+#include "rescore_internal.h"
 
 using namespace emri;
 
@@ -17,7 +18,7 @@ namespace {
 constexpr size_t kLdsLimit = 163840;      // bytes of LDS a gfx950 workgroup may use
 
 struct Layout {
-  size_t seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off, total;
+  size_t seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off, cand_val_off, cand_idx_off, total;
   int seg_stride;
 };
 
@@ -49,8 +50,15 @@ int make_layout(const emri_power *pw, int K, int64_t n_tmpl, int top_k, bool sta
   off += round_up((n4 > 0 ? n4 : 4) * sizeof(MixedSeg), 256);
   L->stat_off = off;
   if (stat_in_ws) off += round_up((size_t)n_tmpl * sizeof(float), 256);
+  // the top-k state (sized for the candidates of a re-scoring mixed call,
+  // which a plain call leaves unused) and the re-scored candidates
+  const int n_cand = top_k > 0 ? rescore_candidates(top_k, n_tmpl) : 0;
   L->topk_off = off;
-  off += topk_workspace_bytes(top_k);
+  off += topk_workspace_bytes(std::max(top_k, n_cand));
+  L->cand_val_off = off;
+  off += round_up((size_t)std::max(n_cand, 1) * sizeof(float), 256);
+  L->cand_idx_off = off;
+  off += round_up((size_t)std::max(n_cand, 1) * sizeof(int64_t), 256);
   L->total = off;
   return EMRI_OK;
 }
@@ -151,14 +159,16 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
                       void *hip_stream, bool static_scratch, int n_harm, const double *ratios) {
   int st = check_sizes(power, K, n_tmpl, top_k);
   if (st) return st;
-  int k_min = 0, k_max = power->n_bins - 1, precision = EMRI_PLAIN;
+  int k_min = 0, k_max = power->n_bins - 1, precision = EMRI_PLAIN, rescore_top = 0;
   if (opts) {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
       if (opts->reserved[i] != 0) return fail(EMRI_EINVAL, "score_opts.reserved must be zero");
     k_min = opts->k_min;
     if (opts->k_max >= 0) k_max = opts->k_max;
     precision = opts->precision;
+    rescore_top = opts->rescore_top;
   }
+  if (rescore_top != 0 && rescore_top != 1) return fail(EMRI_EINVAL, "rescore_top must be 0 or 1");
   if (precision != EMRI_PLAIN && precision != EMRI_MIXED)
     return fail(EMRI_EINVAL, "unknown precision %d", precision);
   const bool mixed = precision == EMRI_MIXED;
@@ -293,7 +303,33 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     }
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "score launch: %s", hipGetErrorString(err));
   }
-  if (top_k > 0) {
+  if (top_k > 0 && mixed && rescore_top && n_tmpl > 0 && power->n_seg > 0) {
+    // the leading candidates of the mixed statistic, re-scored with FP64
+    // positions (the plain statistic), then ordered for the top-k
+    const int n_cand = rescore_candidates(top_k, n_tmpl);
+    float *cand_val = reinterpret_cast<float *>(ws + L.cand_val_off);
+    int64_t *cand_idx = reinterpret_cast<int64_t *>(ws + L.cand_idx_off);
+    err = launch_topk(stat_buf, n_tmpl, n_cand, cand_val, cand_idx, ws + L.topk_off, cus, stream, 0);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "top-k launch: %s", hipGetErrorString(err));
+    RescoreParams r{};
+    r.power = power->data;
+    r.seg = seg;
+    r.coeffs = coeffs;
+    r.stat = stat_buf;
+    r.cand_idx = cand_idx;
+    r.cand_val = cand_val;
+    r.n_tmpl = n_tmpl;
+    r.n_cand = n_cand;
+    r.n_seg = power->n_seg;
+    r.seg_stride = L.seg_stride;
+    r.K = K;
+    r.row_pitch = power->row_pitch;
+    r.k_min = k_min;
+    r.k_max = k_max;
+    err = launch_rescore(r, power->dtype, stream);
+    if (err == hipSuccess) err = launch_rescore_select(cand_val, cand_idx, n_cand, top_k, topk_val, topk_idx, stream);
+    if (err != hipSuccess) return fail(EMRI_EDEVICE, "re-scoring launch: %s", hipGetErrorString(err));
+  } else if (top_k > 0) {
     const int first_pass = (n_tmpl > 0 && !mixed && !harm && !validate && power->n_seg > 0) ? 1 : 0;
     err = launch_topk(stat_buf, n_tmpl, top_k, topk_val, topk_idx, ws + L.topk_off, cus, stream, first_pass);
     if (err != hipSuccess) return fail(EMRI_EDEVICE, "top-k launch: %s", hipGetErrorString(err));

@@ -78,6 +78,9 @@ def test_score_tracks_rejects_bin_range():
     bad = _Opts(0, -1)
     bad.reserved[2] = 1
     assert _score(_power(), opts=bad) == -1
+    bad = _Opts(0, -1, 1)
+    bad.rescore_top = 2
+    assert _score(_power(), opts=bad) == -1
 
 
 def test_workspace_size_grows_with_stat_in_workspace():

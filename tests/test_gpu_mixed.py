@@ -146,6 +146,12 @@ def test_mixed_one_year_full_size_error_report(gpu_lib, K):
     print(f"mixed K={K}: top-100 overlap {overlap}")
     assert overlap >= 99
     assert np.array_equal(_np(res["topk_val"]), stat[_np(res["topk_idx"])])
+    # re-scoring the leading candidates returns the oracle's top-100
+    resc = emri.score_tracks(spec, _t(f0), _t(U), C_d, 100, precision="mixed", rescore_top=True)
+    torch.cuda.synchronize()
+    ridx = _np(resc["topk_idx"])
+    assert set(ridx.tolist()) == true_top
+    assert np.array_equal(ridx, _np(plain["topk_idx"]))
 
 
 def test_mixed_batched_equals_standalone(gpu_lib):
@@ -191,3 +197,39 @@ def test_mixed_wild_coefficients(gpu_lib):
     ok[5:9] = False
     rel = np.abs(mixed["stat"][ok] - plain["stat"][ok]) / plain["stat"][ok]
     assert np.quantile(rel, 0.99) <= 2e-3
+
+
+@pytest.mark.parametrize("n_seg,n_bins,n_tmpl,K,top_k,dtype", [
+    (23, 700, 5000, 8, 32, "f16"),
+    (600, 300, 3000, 3, 16, "f32"),        # more than one chunk of 512 segments, a ragged last run
+    (9, 500, 50, 16, 16, "f16"),           # fewer templates than candidates
+    (9, 500, 10, 4, 16, "f16"),            # top_k larger than the batch: padded
+    (40, 4000, 200_000, 8, 100, "f16"),    # general inputs, many moved bins in the mixed statistic
+])
+def test_mixed_rescore_top_matches_plain(gpu_lib, n_seg, n_bins, n_tmpl, K, top_k, dtype):
+    """rescore_top: the returned top-k is the plain path's top-k, values bit for
+    bit, and the re-scored entries of stat are the plain statistic."""
+    emri = gpu_lib
+    g = np.random.default_rng(400 + n_seg + K)
+    t = 1.0
+    P = g.exponential(size=(n_seg, n_bins))
+    spec = emri.spectrogram_from_power(P, t, dtype)
+    f0 = g.uniform(0.4 * n_bins, 0.6 * n_bins, n_seg)
+    U = g.standard_normal((n_seg, K)) * (0.02 * n_bins)
+    C = g.uniform(-2, 2, (n_tmpl, K)).astype(np.float32)
+    plain = _score(emri, spec, f0, U, C, top_k)
+    mixed = _score(emri, spec, f0, U, C, top_k, precision="mixed")
+    resc = _score(emri, spec, f0, U, C, top_k, precision="mixed", rescore_top=True)
+    kk = min(top_k, n_tmpl)
+    assert np.array_equal(resc["topk_idx"][:kk], plain["topk_idx"][:kk])
+    assert np.array_equal(resc["topk_val"][:kk], plain["topk_val"][:kk])
+    assert np.all(resc["topk_idx"][kk:] == -1) and np.all(np.isneginf(resc["topk_val"][kk:]))
+    assert np.array_equal(resc["stat"][resc["topk_idx"][:kk]], plain["stat"][resc["topk_idx"][:kk]])
+    # entries that were not re-scored keep the mixed statistic
+    changed = np.flatnonzero(resc["stat"] != mixed["stat"])
+    n_cand = min(n_tmpl, max(4 * top_k, 64), 4096)
+    assert changed.size <= n_cand
+    assert np.array_equal(resc["stat"][changed], plain["stat"][changed])
+    # and the top-k agrees with the oracle's on its own candidates
+    o = oracle.score_tracks(_np(spec.power()).astype(np.float64), f0, U, C[resc["topk_idx"][:kk]], t, 0)
+    assert np.max(np.abs(resc["topk_val"][:kk] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
