@@ -77,7 +77,7 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
   bool wild = false;
 #pragma unroll
   for (int s = 0; s < TPL; ++s) {
-    const int64_t j = t0 + (int64_t)s * MIXED_THREADS + tid;
+    const int64_t j = t0 + (int64_t)s * mixed_threads(K) + tid;
     const bool live = j < j_end;
     float cf[4 * KG];
 #pragma unroll
@@ -322,7 +322,7 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
   pipe_publish<PT>(p, pp, lds, half ^ 1);
 }
 
-// One tile: TPL slots of MIXED_THREADS templates against every segment.  Software
+// One tile: TPL slots of mixed_threads(K) templates against every segment.  Software
 // pipelined: while a wave gathers with the products of step n it also issues
 // the matrix products of step n+1 (two steps per loop turn, so the two product
 // buffers swap roles without copies).  Above K = 8 the caller has queued the
@@ -379,11 +379,12 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, const Pipe 
 }
 
 // Copy the piece table of a stream into the front of LDS (before the staging halves).
+template <int NT>
 __device__ __forceinline__ void load_table(const ScoreParams &p, unsigned char *tab) {
   const int n16 = p.mtab_bytes >> 4;
   const uint4 *src = reinterpret_cast<const uint4 *>(p.mtab);
   uint4 *dst = reinterpret_cast<uint4 *>(tab);
-  for (int i = threadIdx.x; i < n16; i += MIXED_THREADS) dst[i] = src[i];
+  for (int i = threadIdx.x; i < n16; i += NT) dst[i] = src[i];
 }
 
 __device__ __forceinline__ unsigned char *staging_base(const ScoreParams &p, unsigned char *lds) {
@@ -415,7 +416,7 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
     run_tile_mixed<KG, T, PT, false>(p, &pp, lds, stage, pc, sum);
 #pragma unroll
   for (int s = 0; s < T; ++s) {
-    const int64_t j = t0 + (int64_t)s * MIXED_THREADS + threadIdx.x;
+    const int64_t j = t0 + (int64_t)s * mixed_threads(K) + threadIdx.x;
     if (j < j_end) p.stat[j] = (float)sum[s];
   }
 }
@@ -426,8 +427,9 @@ __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned
                                                   int64_t j_end) {
   constexpr int TAIL = (TPL + 1) / 2;
   unsigned char *stage = staging_base(p, lds);
-  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * MIXED_THREADS) {
-    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * MIXED_THREADS) {
+  constexpr int NT = mixed_threads(K);
+  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * NT) {
+    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * NT) {
       score_tile_mixed<K, TAIL, PT>(p, lds, stage, t0, j_end);
       break;
     }
@@ -436,9 +438,9 @@ __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned
 }
 
 template <int K, int TPL, typename PT>
-__global__ __launch_bounds__(MIXED_THREADS) void score_mixed_kernel(ScoreParams p) {
+__global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScoreParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-  load_table(p, lds);
+  load_table<mixed_threads(K)>(p, lds);
   init_lds(p, staging_base(p, lds));
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
@@ -448,7 +450,7 @@ __global__ __launch_bounds__(MIXED_THREADS) void score_mixed_kernel(ScoreParams 
 // Batched form of the mixed kernel (work items claimed as in the plain
 // batched kernel; the piece table is reloaded when the stream changes).
 template <int K, int TPL, typename PT>
-__global__ __launch_bounds__(MIXED_THREADS) void score_mixed_batched_kernel(const ScoreParams *__restrict__ params,
+__global__ __launch_bounds__(mixed_threads(K)) void score_mixed_batched_kernel(const ScoreParams *__restrict__ params,
                                                                             const BatchItem *__restrict__ items,
                                                                             int n_items, int *counter) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(MIXED_THREADS) void score_mixed_batched_kernel(cons
     const BatchItem item = load_uniform(items + it);
     const ScoreParams p = load_uniform(params + item.stream);
     if (item.stream != table_of) {     // claim_item's barriers order this after the last reads
-      load_table(p, lds);
+      load_table<mixed_threads(K)>(p, lds);
       table_of = item.stream;
     }
     init_lds(p, staging_base(p, lds));
@@ -468,12 +470,15 @@ __global__ __launch_bounds__(MIXED_THREADS) void score_mixed_batched_kernel(cons
   }
 }
 
-// Templates per lane of the 1024-thread workgroup (128 VGPRs per wave at four
-// waves per SIMD; a tile is as large as with 512 threads and twice the
-// templates per lane, but a SIMD has twice the waves to hide the latency of
-// the gathers and the matrix products behind: one-year, 1e8 templates,
-// K = 8 9.51 -> 8.39 ms, K = 16 16.14 -> 14.99 ms).
-constexpr int mixed_tpl(int K) { return K <= 4 ? 4 : (K <= 8 ? 3 : 2); }
+// Templates per lane: up to K = 8 in 1024-thread workgroups (128 VGPRs per
+// wave at four waves per SIMD; a tile is as large as with 512 threads and
+// twice the templates per lane, but a SIMD has twice the waves to hide the
+// latency of the gathers and the matrix products behind: one-year, 1e8
+// templates, K = 8 9.51 -> 8.39 ms, K = 16 16.14 -> 14.99 ms), above in
+// 768-thread workgroups with three templates per lane (K = 16 12.95 -> 12.39
+// ms against two per lane at 1024 threads; at K = 8 four per lane at 768
+// threads measured the same as three at 1024).
+constexpr int mixed_tpl(int K) { return K <= 4 ? 4 : 3; }
 
 template <typename Kern>
 hipError_t set_lds(Kern kern, size_t lds) {
@@ -486,7 +491,7 @@ hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_
   auto kern = score_mixed_kernel<K, mixed_tpl(K), PT>;
   hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(MIXED_THREADS), lds, stream, p);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(mixed_threads(K)), lds, stream, p);
   return hipGetLastError();
 }
 
@@ -495,7 +500,7 @@ hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
   auto kern = score_mixed_batched_kernel<K, mixed_tpl(K), PT>;
   hipError_t err = set_lds(kern, b.lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(MIXED_THREADS), b.lds, stream, b.params, b.items, b.n_items, b.counter);
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(mixed_threads(K)), b.lds, stream, b.params, b.items, b.n_items, b.counter);
   return hipGetLastError();
 }
 
@@ -517,7 +522,7 @@ hipError_t dispatch_mixed_batched(int K, const BatchLaunch &b, hipStream_t strea
 }  // namespace
 
 int mixed_templates_per_lane(int K) { return mixed_tpl(K); }
-int mixed_tile_templates(int K) { return mixed_tpl(K) * MIXED_THREADS; }
+int mixed_tile_templates(int K) { return mixed_tpl(K) * mixed_threads(K); }
 
 hipError_t launch_score_mixed(const ScoreParams &p, int K, int dtype, int grid, size_t lds, hipStream_t stream) {
   using Ks = std::make_integer_sequence<int, MIXED_MAX_K>;

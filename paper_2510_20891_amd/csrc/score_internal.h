@@ -55,10 +55,12 @@ struct MixedSeg {
 };
 
 constexpr int MIXED_MAX_K = 16;
-// The mixed kernel runs 1024-thread workgroups (four waves per SIMD); the
-// first SCORE_WAVES of its waves stage the rows.
-constexpr int MIXED_THREADS = 1024;
-static_assert(MIXED_THREADS % SCORE_THREADS == 0, "the staging waves are a prefix of the workgroup");
+// Workgroup size of the mixed kernel: 1024 threads (four waves per SIMD, 128
+// VGPRs each) up to K = 8, 768 (three waves, 168 VGPRs) above; the first
+// SCORE_WAVES of its waves stage the rows.
+__host__ __device__ constexpr int mixed_threads(int K) { return K <= 8 ? 1024 : 768; }
+static_assert(mixed_threads(1) >= SCORE_THREADS && mixed_threads(16) >= SCORE_THREADS && mixed_threads(16) % 64 == 0,
+              "the staging waves are a prefix of the workgroup");
 __host__ __device__ constexpr int mixed_groups(int K) { return (K + 3) / 4; }
 // bytes of the BF16 piece table per segment: 3 pieces x groups x 4 values x 2 bytes
 __host__ __device__ constexpr int mixed_row_bytes(int K) { return 3 * mixed_groups(K) * 8; }

@@ -65,7 +65,7 @@ def test_mixed_short_and_ragged_segment_counts(gpu_lib, K, n_seg, n_tmpl):
     segments in flight, at K = 16 one.  With 7000 templates the 14 workgroups
     get 500 templates each, so only the half-size tail tile runs (with idle
     lanes); with 1.6e6 templates each of the (up to 256) workgroups gets about
-    6250, so full tiles of TPL x 1024 templates (2048 to 4096) run before a
+    6250, so full tiles of TPL x 768 or x 1024 templates (2304 to 4096) run before a
     ragged tail."""
     emri = gpu_lib
     g = np.random.default_rng(1000 + 17 * K + n_seg + n_tmpl)
