@@ -737,7 +737,7 @@ def main() -> int:
                    "positions": "f64", "power": "f32", "statistic": "f32 runs of 8, f64 across"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "score_fast_kernel<K=8, TPL=10, f32>",
+                     "kernel": "score_fast_kernel<K=8, TPL=5, f32> (1024 threads)",
                      "kernel_ms": ms_kernel, "algorithmic_bytes_per_launch": b_eff},
         "cpu_baseline": cpu,
         "one_off": {"build_sfts_ms": t_sfts_ms, "build_basis_s": t_basis},

@@ -3,9 +3,10 @@
 // the basis product of Eq. (10), bin width 1/T_SFT of Sec. II B).
 //
 // Layout and schedule (MI355X / gfx950):
-//   * A persistent grid of one 512-thread workgroup per CU.  Workgroup g owns a
-//     contiguous range of templates and walks it in tiles of TPL*512 templates:
-//     lane l holds TPL templates (j = tile + s*512 + l), their K coefficients
+//   * A persistent grid of one workgroup per CU (NT = 1024 threads for a
+//     standalone launch, 512 in the batched one).  Workgroup g owns a
+//     contiguous range of templates and walks it in tiles of TPL*NT templates:
+//     lane l holds TPL templates (j = tile + s*NT + l), their K coefficients
 //     widened to FP64 and kept in VGPRs for the whole tile.
 //   * Each power row P[alpha, 0..n_bins) is staged in LDS by asynchronous
 //     global->LDS copies (global_load_lds_dwordx4, 1 KB per wave instruction).
@@ -85,7 +86,7 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   for (int s = 0; s < TPL; ++s) acc[s] = 0.0f;
   const Pipe pp = pipe_init<PT>(p);
   const int G = p.G;
-  pipe_issue(p, pp, lds, 0, 0);
+  if (pp.wave < SCORE_WAVES) pipe_issue(p, pp, lds, 0, 0);
   pipe_publish<PT>(p, pp, lds, 0);
   int addr[TPL];
   double f0t, ut[K > 0 ? K : 1];
@@ -97,7 +98,7 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0): nothing scalar in flight entering the loop
   int half = 0;
   for (int r0 = 0; r0 < p.n_seg; r0 += G) {
-    pipe_issue(p, pp, lds, r0 + G, half ^ 1);
+    if (pp.wave < SCORE_WAVES) pipe_issue(p, pp, lds, r0 + G, half ^ 1);
     for (int i = 0; i < G; ++i) {
       const int r = r0 + i;
       if (r >= p.n_seg) break;
@@ -145,8 +146,9 @@ __device__ __forceinline__ void run_tile(const ScoreParams &p, unsigned char *ld
   }
 }
 
-// One tile of T slots (T x 512 templates starting at t0, clipped to j_end).
-template <int K, int T, typename PT>
+// One tile of T slots (T x NT templates starting at t0, clipped to j_end; NT
+// threads per workgroup).
+template <int K, int T, typename PT, int NT = SCORE_THREADS>
 __device__ __forceinline__ void score_tile(const ScoreParams &p, unsigned char *lds, int64_t t0, int64_t j_end,
                                            const double (&bound_u)[K > 0 ? K : 1], double bound_f0) {
   const int tid = threadIdx.x;
@@ -154,7 +156,7 @@ __device__ __forceinline__ void score_tile(const ScoreParams &p, unsigned char *
   bool wild = false;
 #pragma unroll
   for (int s = 0; s < T; ++s) {
-    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+    const int64_t j = t0 + (int64_t)s * NT + tid;
     const bool live = j < j_end;
     float cf[K > 0 ? K : 1];
     if constexpr (K % 4 == 0) {
@@ -185,7 +187,7 @@ __device__ __forceinline__ void score_tile(const ScoreParams &p, unsigned char *
     run_tile<K, T, PT, false>(p, lds, c, sum);
 #pragma unroll
   for (int s = 0; s < T; ++s) {
-    const int64_t j = t0 + (int64_t)s * SCORE_THREADS + tid;
+    const int64_t j = t0 + (int64_t)s * NT + tid;
     if (j < j_end) p.stat[j] = (float)sum[s];
   }
 }
@@ -193,7 +195,7 @@ __device__ __forceinline__ void score_tile(const ScoreParams &p, unsigned char *
 // Score templates [j_begin, j_end) of one stream (the workgroup's share) in
 // tiles of TPL slots; a last tile that fits in half as many slots runs with
 // half (the per-template arithmetic and order do not depend on the tile).
-template <int K, int TPL, typename PT>
+template <int K, int TPL, typename PT, int NT = SCORE_THREADS>
 __device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
                                             int64_t j_end) {
   constexpr int TAIL = (TPL + 1) / 2;
@@ -202,12 +204,12 @@ __device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char 
 #pragma unroll
   for (int k = 0; k < K; ++k) bound_u[k] = bnd_src[1 + k];
   const double bound_f0 = bnd_src[0];
-  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * SCORE_THREADS) {
-    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * SCORE_THREADS) {
-      score_tile<K, TAIL, PT>(p, lds, t0, j_end, bound_u, bound_f0);
+  for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * NT) {
+    if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * NT) {
+      score_tile<K, TAIL, PT, NT>(p, lds, t0, j_end, bound_u, bound_f0);
       break;
     }
-    score_tile<K, TPL, PT>(p, lds, t0, j_end, bound_u, bound_f0);
+    score_tile<K, TPL, PT, NT>(p, lds, t0, j_end, bound_u, bound_f0);
   }
 }
 
@@ -217,6 +219,7 @@ __device__ __forceinline__ void score_range(const ScoreParams &p, unsigned char 
 // histogram of the 12-bit leading key digit, counted as the top-k's own first
 // pass does (an 8-bin register window per wave); the workgroups merge it in
 // two levels and the last one picks the digit.
+template <int NT>
 __device__ void first_key_pass_of_range(const ScoreParams &p, unsigned char *lds, int64_t j_begin, int64_t j_end) {
   constexpr int SHIFT = 20, WIDTH = 12;
   constexpr uint32_t MASK = (1u << WIDTH) - 1u;
@@ -261,22 +264,30 @@ __device__ void first_key_pass_of_range(const ScoreParams &p, unsigned char *lds
   }
   if (count > 0) add_window(lh, base, packed);
   flush_hist(lh, p.topk->ghist[blockIdx.x % TOPK_GROUPS], TOPK_HIST);
-  if (finish_pass<SCORE_THREADS>(p.topk, TOPK_HIST, (int)blockIdx.x, (int)gridDim.x)) {
+  if (finish_pass<NT>(p.topk, TOPK_HIST, (int)blockIdx.x, (int)gridDim.x)) {
     TopkJob job{};
     job.st = p.topk;
     job.kk = p.topk_kk;
-    select_digit<true, SCORE_THREADS>(job, lh, SHIFT, WIDTH, true, false, false);
+    select_digit<true, NT>(job, lh, SHIFT, WIDTH, true, false, false);
   }
 }
 
+// The standalone kernel runs FAST_THREADS-thread workgroups (four waves per
+// SIMD with 128 VGPRs each, half the templates per lane of the 512-thread
+// batched kernel, so a tile is as large): twice the waves to hide the FP64
+// multiply-add chains and the gathers behind.  The first SCORE_WAVES waves
+// stage the rows.  One-year, K = 8: 1e7 templates FP32 1.49 -> 1.39 ms, 1e8
+// templates 12.85 -> 11.28 ms; K = 16, 1e8: 26.8 -> 23.2 ms (FP32).
+constexpr int FAST_THREADS = 1024;
+
 template <int K, int TPL, typename PT>
-__global__ __launch_bounds__(SCORE_THREADS) void score_fast_kernel(ScoreParams p) {
+__global__ __launch_bounds__(FAST_THREADS) void score_fast_kernel(ScoreParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   init_lds(p, lds);
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
-  score_range<K, TPL, PT>(p, lds, j_begin, j_end);
-  if (p.topk) first_key_pass_of_range(p, lds, j_begin, j_end);
+  score_range<K, TPL, PT, FAST_THREADS>(p, lds, j_begin, j_end);
+  if (p.topk) first_key_pass_of_range<FAST_THREADS>(p, lds, j_begin, j_end);
 }
 
 // Batched form: one persistent launch over many streams.  Workgroups claim
@@ -483,13 +494,14 @@ constexpr int tpl_alt(int K) {
   return t < 1 ? 1 : t;
 }
 constexpr bool has_alt(int K) { return K == 8 || K == 16; }
-// The standalone kernel at K = 8 with FP32 power fits a tenth slot in its 256
-// VGPRs without spilling: fewer tiles, so each row is staged fewer times
-// (measured ~2 % faster).  With FP16 power it does not pay, and the batched
-// kernel, which holds more state, would spill.
+// The standalone kernel: half the 512-thread kernel's slots (rounded up), in
+// 1024-thread workgroups.  At K = 8 that is five (the 512-thread kernel held
+// a tenth slot at FP32, ~2 % faster than nine); at K = 16 three, which spill
+// a few VGPRs in the tile prologue and still measured fastest.
 template <int K, typename PT>
 constexpr int tpl_fast() {
-  return (K == 8 && sizeof(PT) == 4) ? 10 : tpl_for(K);
+  constexpr int t512 = (K == 8 && sizeof(PT) == 4) ? 10 : tpl_for(K);
+  return (t512 + 1) / 2;
 }
 
 template <typename Kern>
@@ -504,7 +516,7 @@ hipError_t launch_fast_k(const ScoreParams &p, int grid, size_t lds, hipStream_t
   auto kern = score_fast_kernel<K, TPL, PT>;
   hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(SCORE_THREADS), lds, stream, p);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(FAST_THREADS), lds, stream, p);
   return hipGetLastError();
 }
 
