@@ -18,7 +18,7 @@ namespace {
 constexpr size_t kLdsLimit = 163840;      // bytes of LDS a gfx950 workgroup may use
 
 struct Layout {
-  size_t seg_off, bound_off, mtab_off, mseg_off, stat_off, topk_off, cand_val_off, cand_idx_off, total;
+  size_t seg_off, bound_off, mtab_off, mseg_off, redo_off, stat_off, topk_off, cand_val_off, cand_idx_off, total;
   int seg_stride;
 };
 
@@ -48,6 +48,8 @@ int make_layout(const emri_power *pw, int K, int64_t n_tmpl, int top_k, bool sta
   off += round_up((n4 > 0 ? n4 : 4) * mixed_row_bytes(MIXED_MAX_K), 256);
   L->mseg_off = off;
   off += round_up((n4 > 0 ? n4 : 4) * sizeof(MixedSeg), 256);
+  L->redo_off = off;                             // tile queue of the reduced-chain launch
+  off += round_up(MIXED_REDO_BYTES, 256);
   L->stat_off = off;
   if (stat_in_ws) off += round_up((size_t)n_tmpl * sizeof(float), 256);
   // the top-k state (sized for the candidates of a re-scoring mixed call,
@@ -250,6 +252,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     if (mixed) {
       job.mtab = ws + L.mtab_off;
       job.mseg = ws + L.mseg_off;
+      if (K > 12) job.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
     }
     if (top_k > 0) job.topk = reinterpret_cast<TopkState *>(ws + L.topk_off);
     err = launch_score_prep(job, stream);
@@ -278,6 +281,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
       p.mtab = ws + L.mtab_off;
       p.mseg = ws + L.mseg_off;
       p.mtab_bytes = mtab_bytes;
+      if (K > 12) p.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
     }
     // a plain launch with a top-k also runs the top-k's first key pass
     size_t lds = sg.lds;

@@ -70,11 +70,13 @@ __device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w 
 // Returns true if any of them could place a track at |x| >= 2^21 bins (huge
 // or non-finite values), from the per-segment bounds of prep.
 template <int K, int KG, int TPL>
-__device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, int64_t j_end, Pieces<KG, TPL> &pc) {
+__device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, int64_t j_end, Pieces<KG, TPL> &pc,
+                                            bool &tail_small) {
   const int tid = threadIdx.x;
   typedef const __attribute__((address_space(4))) double *const_dptr;
   const_dptr bnd = (const_dptr)p.bound;
   bool wild = false;
+  tail_small = true;
 #pragma unroll
   for (int s = 0; s < TPL; ++s) {
     const int64_t j = t0 + (int64_t)s * mixed_threads(K) + tid;
@@ -101,9 +103,22 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
     // sum, so b < 2^21 (1 - 1e-5) implies the exact bound is below 2^21; then
     // |I + D| < 2^22 and the FP32 rounding of D + M is exact
     float b = (float)bnd[0];
+    float bg[KG];
 #pragma unroll
-    for (int k = 0; k < K; ++k) b += __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
+    for (int g = 0; g < KG; ++g) bg[g] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float t = __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
+      b += t;
+      bg[k / 4] += t;
+    }
     wild |= !(b < 2097152.0f * 0.99999f);
+    if constexpr (KG == 4) {
+      // the reduced chain's limits, less a margin of 1 % for the FP32
+      // rounding of these sums (non-finite values fail the test)
+      const float all = bg[0] + bg[1] + bg[2] + bg[3];
+      tail_small &= bg[2] <= 0x1p-9f * 0.99f * all && bg[3] <= 0x1p-17f * 0.99f * all;
+    }
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
       // pieces of coefficients 4g .. 4g+3, two per conversion: each remainder
@@ -125,28 +140,57 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
   return wild;
 }
 
+// Reduced chain (RED, four coefficient groups only).  Above K = 12 the last
+// groups of an SVD basis carry little: over the one-year box at K = 16 the
+// bound sum_k |c_k| max_alpha |U T| of group 2 is at most 1.3e-3, and of
+// group 3 1.7e-6, of a template's whole bound.  The reduced chain keeps,
+// for group 2, the products of piece order <= 1 (c0 u0, c0 u1, c1 u0) and,
+// for group 3, c0 u0 alone: the terms left out are below 2^-16 (group 2)
+// and 2^-8 (group 3) of the group's bound, so for a template whose group
+// bounds are at most 2^-9 and 2^-17 of its whole bound (tail_small) they
+// change the position by less than about 2^-24.4 of that bound, one
+// rounding of the FP32 sum.  A wave of the reduced launch that holds a
+// template outside those limits (or a wild one) queues its tile, and a
+// second launch scores the queued tiles again with the full chains.
+template <int KG, bool RED>
+constexpr bool product_kept(int i) {
+  const int p = i / KG, g = i % KG;            // pair (smallest first) and group
+  return !RED || !((g == KG - 2 && p < 3) || (g == KG - 1 && p < 5));
+}
+template <int KG, bool RED>
+constexpr int products_in_part(int part) {
+  constexpr int NI = kPairs * KG;
+  int n = 0;
+  for (int i = part * NI / 4; i < (part + 1) * NI / 4; ++i) n += product_kept<KG, RED>(i) ? 1 : 0;
+  return n;
+}
+
 // Part PART of 4 of the matrix products of one staging step: instructions
 // [PART*NI/4, (PART+1)*NI/4) of every slot's chain (NI = 6*KG, smallest
-// products first); the chains start from phi.
-template <int KG, int TPL, int PART>
+// products first; with RED the products above are left out); the chains
+// start from phi.
+template <int KG, int TPL, int PART, bool RED>
 __device__ __forceinline__ void products_part(const short4_t (&ua)[3][KG], const float4_t &phi,
                                               const Pieces<KG, TPL> &pc, float4_t (&d)[TPL]) {
   constexpr int NI = kPairs * KG;
+  static_assert(product_kept<KG, RED>(0), "every chain starts from phi");
 #pragma unroll
-  for (int i = PART * NI / 4; i < (PART + 1) * NI / 4; ++i)
+  for (int i = PART * NI / 4; i < (PART + 1) * NI / 4; ++i) {
+    if (!product_kept<KG, RED>(i)) continue;
 #pragma unroll
     for (int s = 0; s < TPL; ++s)
       d[s] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(ua[pair_u(i / KG)][i % KG], pc.v[s][pair_c(i / KG)][i % KG],
                                                     i == 0 ? phi : d[s], 0, 0, 0);
+  }
 }
 
-template <int KG, int TPL>
+template <int KG, int TPL, bool RED>
 __device__ __forceinline__ void step_products(const short4_t (&ua)[3][KG], const float4_t &phi,
                                               const Pieces<KG, TPL> &pc, float4_t (&d)[TPL]) {
-  products_part<KG, TPL, 0>(ua, phi, pc, d);
-  products_part<KG, TPL, 1>(ua, phi, pc, d);
-  products_part<KG, TPL, 2>(ua, phi, pc, d);
-  products_part<KG, TPL, 3>(ua, phi, pc, d);
+  products_part<KG, TPL, 0, RED>(ua, phi, pc, d);
+  products_part<KG, TPL, 1, RED>(ua, phi, pc, d);
+  products_part<KG, TPL, 2, RED>(ua, phi, pc, d);
+  products_part<KG, TPL, 3, RED>(ua, phi, pc, d);
 }
 
 // Operands of the products of one staging step r0: the A rows (segment
@@ -214,7 +258,7 @@ __device__ __forceinline__ void interleave_products() {
 // gather in-bounds stale data that is not added.  GUARD: this step may reach
 // past n_seg (the last step; others add without a test); FOLD: the FP32 run
 // ends here and is added into the FP64 sums (every second step, and the last).
-template <int KG, int TPL, typename PT, bool WILD, bool GUARD, bool FOLD>
+template <int KG, int TPL, typename PT, bool WILD, bool RED, bool GUARD, bool FOLD>
 __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp, const unsigned char *tab,
                                            unsigned char *lds, const Pieces<KG, TPL> &pc, int r0, int half,
                                            const float4_t (&dc)[TPL], const double (&Ic)[4], const float (&Mc)[4],
@@ -222,7 +266,6 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
                                            const BinClamp &bcl, float (&acc)[TPL],
                                            double (&sum)[TPL]) {
   constexpr int E = Elem<PT>::bytes;
-  constexpr int NQ = kPairs * KG / 4 * TPL;       // products per quarter (lower bound)
   static_assert(TPL < 16, "lgkmcnt holds at most 15 outstanding gathers");
   if (pp.wave < SCORE_WAVES) pipe_issue(p, pp, lds, r0 + 4, half ^ 1);
 #pragma unroll
@@ -266,17 +309,29 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
 #pragma unroll
       for (int s = 0; s < TPL; ++s) v[r % NV][s] = Elem<PT>::raw(addr[s]);
       __builtin_amdgcn_sched_barrier(0);
-      if (r == 0) products_part<KG, TPL, 0>(op.ua, op.phi, pc, dn);
-      if (r == 1) products_part<KG, TPL, 1>(op.ua, op.phi, pc, dn);
-      if (r == 2) products_part<KG, TPL, 2>(op.ua, op.phi, pc, dn);
-      if (r == 3) products_part<KG, TPL, 3>(op.ua, op.phi, pc, dn);
+      if (r == 0) products_part<KG, TPL, 0, RED>(op.ua, op.phi, pc, dn);
+      if (r == 1) products_part<KG, TPL, 1, RED>(op.ua, op.phi, pc, dn);
+      if (r == 2) products_part<KG, TPL, 2, RED>(op.ua, op.phi, pc, dn);
+      if (r == 3) products_part<KG, TPL, 3, RED>(op.ua, op.phi, pc, dn);
       __builtin_amdgcn_sched_barrier(0);
     } else {
-      if (r == 0) products_part<KG, TPL, 0>(op.ua, op.phi, pc, dn);
-      if (r == 1) products_part<KG, TPL, 1>(op.ua, op.phi, pc, dn);
-      if (r == 2) products_part<KG, TPL, 2>(op.ua, op.phi, pc, dn);
-      if (r == 3) products_part<KG, TPL, 3>(op.ua, op.phi, pc, dn);
-      interleave_products<NQ>();
+      // each quarter's products interleaved one for one with the vector work
+      if (r == 0) {
+        products_part<KG, TPL, 0, RED>(op.ua, op.phi, pc, dn);
+        interleave_products<products_in_part<KG, RED>(0) * TPL>();
+      }
+      if (r == 1) {
+        products_part<KG, TPL, 1, RED>(op.ua, op.phi, pc, dn);
+        interleave_products<products_in_part<KG, RED>(1) * TPL>();
+      }
+      if (r == 2) {
+        products_part<KG, TPL, 2, RED>(op.ua, op.phi, pc, dn);
+        interleave_products<products_in_part<KG, RED>(2) * TPL>();
+      }
+      if (r == 3) {
+        products_part<KG, TPL, 3, RED>(op.ua, op.phi, pc, dn);
+        interleave_products<products_in_part<KG, RED>(3) * TPL>();
+      }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int s = 0; s < TPL; ++s) v[r % NV][s] = Elem<PT>::raw(addr[s]);
@@ -327,7 +382,7 @@ __device__ __forceinline__ void mixed_step(const ScoreParams &p, const Pipe &pp,
 // the matrix products of step n+1 (two steps per loop turn, so the two product
 // buffers swap roles without copies).  Above K = 8 the caller has queued the
 // first rows' copies (`queued`).
-template <int KG, int TPL, typename PT, bool WILD>
+template <int KG, int TPL, typename PT, bool WILD, bool RED>
 __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, const Pipe *queued, unsigned char *tab,
                                                unsigned char *lds, const Pieces<KG, TPL> &pc, double (&sum)[TPL]) {
   float acc[TPL];
@@ -353,7 +408,7 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, const Pipe 
   if (p.n_seg > 0) {
     const MixedSeg *ms = reinterpret_cast<const MixedSeg *>(p.mseg);
     issue_operands<KG>(tab, ms, 0, op);
-    step_products<KG, TPL>(op.ua, op.phi, pc, da);
+    step_products<KG, TPL, RED>(op.ua, op.phi, pc, da);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       Ia[r] = op.I[r];
@@ -367,14 +422,14 @@ __device__ __forceinline__ void run_tile_mixed(const ScoreParams &p, const Pipe 
   // whole pairs of steps, then the last one or two steps (1 to 7 segments)
   int r0 = 0;
   for (; r0 + 8 <= p.n_seg; r0 += 8) {
-    mixed_step<KG, TPL, PT, WILD, false, false>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
-    mixed_step<KG, TPL, PT, WILD, false, true>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, Mb, da, Ia, Ma, op, bcl, acc, sum);
+    mixed_step<KG, TPL, PT, WILD, RED, false, false>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
+    mixed_step<KG, TPL, PT, WILD, RED, false, true>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, Mb, da, Ia, Ma, op, bcl, acc, sum);
   }
   if (r0 + 4 < p.n_seg) {
-    mixed_step<KG, TPL, PT, WILD, false, false>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
-    mixed_step<KG, TPL, PT, WILD, true, true>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, Mb, da, Ia, Ma, op, bcl, acc, sum);
+    mixed_step<KG, TPL, PT, WILD, RED, false, false>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
+    mixed_step<KG, TPL, PT, WILD, RED, true, true>(p, pp, tab, lds, pc, r0 + 4, 1, db, Ib, Mb, da, Ia, Ma, op, bcl, acc, sum);
   } else if (r0 < p.n_seg) {
-    mixed_step<KG, TPL, PT, WILD, true, true>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
+    mixed_step<KG, TPL, PT, WILD, RED, true, true>(p, pp, tab, lds, pc, r0, 0, da, Ia, Ma, db, Ib, Mb, op, bcl, acc, sum);
   }
 }
 
@@ -391,7 +446,7 @@ __device__ __forceinline__ unsigned char *staging_base(const ScoreParams &p, uns
   return lds + ((p.mtab_bytes + 1023) & ~1023);
 }
 
-template <int K, int T, typename PT>
+template <int K, int T, typename PT, bool RED>
 __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned char *lds, unsigned char *stage,
                                                  int64_t t0, int64_t j_end) {
   constexpr int KG = (K + 3) / 4;
@@ -406,14 +461,27 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
     if (pp.wave < SCORE_WAVES) pipe_issue(p, pp, stage, 0, 0);
   }
   Pieces<KG, T> pc;
-  const bool wild = load_pieces<K, KG, T>(p, t0, j_end, pc);
+  bool tail_small;
+  const bool wild = load_pieces<K, KG, T>(p, t0, j_end, pc, tail_small);
   double sum[T];
 #pragma unroll
   for (int s = 0; s < T; ++s) sum[s] = 0.0;
-  if (__any(wild))
-    run_tile_mixed<KG, T, PT, true>(p, &pp, lds, stage, pc, sum);
-  else
-    run_tile_mixed<KG, T, PT, false>(p, &pp, lds, stage, pc, sum);
+  if constexpr (RED) {
+    // one chain only: a wave holding a template it does not cover queues the
+    // tile for the full chains (waves of one tile may queue it more than once;
+    // the full chains then write the same values again)
+    if (__any(wild || !tail_small) && (threadIdx.x & 63) == 0) {
+      const unsigned e = atomicAdd(p.redo, 1u);
+      const int64_t t_end = t0 + (int64_t)T * mixed_threads(K) < j_end ? t0 + (int64_t)T * mixed_threads(K) : j_end;
+      if (e < (unsigned)MIXED_REDO_CAP)
+        reinterpret_cast<uint2 *>(p.redo + 4)[e] = make_uint2((unsigned)t0, (unsigned)t_end);
+    }
+    run_tile_mixed<KG, T, PT, false, true>(p, &pp, lds, stage, pc, sum);
+  } else if (__any(wild)) {
+    run_tile_mixed<KG, T, PT, true, false>(p, &pp, lds, stage, pc, sum);
+  } else {
+    run_tile_mixed<KG, T, PT, false, false>(p, &pp, lds, stage, pc, sum);
+  }
 #pragma unroll
   for (int s = 0; s < T; ++s) {
     const int64_t j = t0 + (int64_t)s * mixed_threads(K) + threadIdx.x;
@@ -422,7 +490,7 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
 }
 
 // Tiles of TPL slots; a last tile that fits in half as many slots runs with half.
-template <int K, int TPL, typename PT>
+template <int K, int TPL, typename PT, bool RED = false>
 __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
                                                   int64_t j_end) {
   constexpr int TAIL = (TPL + 1) / 2;
@@ -430,21 +498,41 @@ __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned
   constexpr int NT = mixed_threads(K);
   for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * NT) {
     if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * NT) {
-      score_tile_mixed<K, TAIL, PT>(p, lds, stage, t0, j_end);
+      score_tile_mixed<K, TAIL, PT, RED>(p, lds, stage, t0, j_end);
       break;
     }
-    score_tile_mixed<K, TPL, PT>(p, lds, stage, t0, j_end);
+    score_tile_mixed<K, TPL, PT, RED>(p, lds, stage, t0, j_end);
   }
 }
 
-template <int K, int TPL, typename PT>
+// MODE 0: the full chains over the workgroup's range; MODE 1: the reduced
+// chain (queues the tiles it does not cover in p.redo); MODE 2: the full
+// chains over the tiles the reduced launch queued (grid-strided; nothing if
+// the queue overflowed); MODE 3: the full chains over the workgroup's range
+// if the queue overflowed (nothing otherwise).
+template <int K, int TPL, typename PT, int MODE>
 __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScoreParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  if constexpr (MODE >= 2) {
+    const unsigned n_redo = __builtin_amdgcn_readfirstlane(*(volatile unsigned *)p.redo);
+    if (MODE == 3 ? n_redo <= (unsigned)MIXED_REDO_CAP : (n_redo > (unsigned)MIXED_REDO_CAP || blockIdx.x >= n_redo))
+      return;
+    if constexpr (MODE == 2) {
+      load_table<mixed_threads(K)>(p, lds);
+      init_lds(p, staging_base(p, lds));
+      const uint2 *q = reinterpret_cast<const uint2 *>(p.redo + 4);
+      for (unsigned e = blockIdx.x; e < n_redo; e += gridDim.x) {
+        const uint2 t = q[e];
+        score_tile_mixed<K, TPL, PT, false>(p, lds, staging_base(p, lds), (int64_t)t.x, (int64_t)t.y);
+      }
+      return;
+    }
+  }
   load_table<mixed_threads(K)>(p, lds);
   init_lds(p, staging_base(p, lds));
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
-  score_range_mixed<K, TPL, PT>(p, lds, j_begin, j_end);
+  score_range_mixed<K, TPL, PT, MODE == 1>(p, lds, j_begin, j_end);
 }
 
 // Batched form of the mixed kernel (work items claimed as in the plain
@@ -486,13 +574,30 @@ hipError_t set_lds(Kern kern, size_t lds) {
                              (int)lds);
 }
 
-template <int K, typename PT>
-hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
-  auto kern = score_mixed_kernel<K, mixed_tpl(K), PT>;
+template <int K, typename PT, int MODE>
+hipError_t launch_mixed_mode(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
+  auto kern = score_mixed_kernel<K, mixed_tpl(K), PT, MODE>;
   hipError_t err = set_lds(kern, lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(mixed_threads(K)), lds, stream, p);
   return hipGetLastError();
+}
+
+// Above K = 12 (with a tile queue in p.redo, whose count the prep kernel of
+// the call cleared): the reduced launch, then the full chains over the tiles
+// it queued (workgroups past the queue's length return at once), then over
+// the whole batch only if the queue overflowed.
+template <int K, typename PT>
+hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
+  if constexpr (mixed_groups(K) == 4) {
+    if (p.redo) {
+      hipError_t err = launch_mixed_mode<K, PT, 1>(p, grid, lds, stream);
+      if (err == hipSuccess) err = launch_mixed_mode<K, PT, 2>(p, grid, lds, stream);
+      if (err == hipSuccess) err = launch_mixed_mode<K, PT, 3>(p, grid, lds, stream);
+      return err;
+    }
+  }
+  return launch_mixed_mode<K, PT, 0>(p, grid, lds, stream);
 }
 
 template <int K, typename PT>

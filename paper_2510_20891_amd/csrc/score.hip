@@ -382,6 +382,7 @@ __device__ __forceinline__ void prep_one(const PrepJob &job, bool reset_topk) {
   const double t_sft = job.t_sft;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0 && job.near_tie) *job.near_tie = 0ull;
+  if (threadIdx.x == 0 && job.redo) *job.redo = 0u;
   if (job.topk && reset_topk) topk_state_reset(job.topk, 0, 1);
   for (int a = threadIdx.x; a < n_seg; a += blockDim.x) {
     job.seg[(size_t)a * stride] = f0[a] * t_sft;

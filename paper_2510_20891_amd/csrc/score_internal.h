@@ -37,6 +37,8 @@ struct ScoreParams {
   const void *mseg;           // per segment: MixedSeg
   int mtab_bytes;             // bytes of mtab for round_up(n_seg, 4) segments (staged in LDS first)
   float one;                  // 1.0f: FP16 power is added as fma(P, one, acc), one instruction
+  unsigned *redo;             // above K = 12: the reduced-chain launch's queue of tiles for the
+                              // full chains (MIXED_REDO_BYTES; count cleared by the prep kernel), or null
   // standalone plain launches with a top-k: the top-k state whose first key
   // pass the scoring workgroups run over their own statistics, or null
   TopkState *topk;
@@ -55,6 +57,12 @@ struct MixedSeg {
 };
 
 constexpr int MIXED_MAX_K = 16;
+// Queue of tiles the reduced-chain mixed launch leaves to the full chains:
+// word 0 counts the entries claimed; entry e, a pair of 32-bit words (first
+// template, end of the tile), starts at byte 16 + 8e.  A count above the
+// capacity sends the whole batch to the full chains.
+constexpr int MIXED_REDO_CAP = 1024;
+constexpr size_t MIXED_REDO_BYTES = 16 + 8 * (size_t)MIXED_REDO_CAP;
 // Workgroup size of the mixed kernel: 1024 threads (four waves per SIMD, 128
 // VGPRs each) up to K = 8, 768 (three waves, 168 VGPRs) above; the first
 // SCORE_WAVES of its waves stage the rows.
@@ -87,6 +95,7 @@ struct PrepJob {
   void *mtab;                  // mixed-precision tables, or null
   void *mseg;
   TopkState *topk;             // top-k state to reset, or null
+  unsigned *redo;              // tile queue of the reduced-chain mixed launch (count to clear), or null
 };
 
 // Launch shape of a batched scoring launch (device tables live in the workspace).

@@ -233,3 +233,54 @@ def test_mixed_rescore_top_matches_plain(gpu_lib, n_seg, n_bins, n_tmpl, K, top_
     # and the top-k agrees with the oracle's on its own candidates
     o = oracle.score_tracks(_np(spec.power()).astype(np.float64), f0, U, C[resc["topk_idx"][:kk]], t, 0)
     assert np.max(np.abs(resc["topk_val"][:kk] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
+
+
+@pytest.mark.parametrize("case", ["few_queued", "all_queued", "queue_overflow"])
+def test_mixed_reduced_chain_queue(gpu_lib, case):
+    """Above K = 12 a standalone mixed call runs the reduced chain (order <= 1
+    products for coefficients 8..11, the leading product alone for 12..15) and
+    queues, per wave, the tiles holding a template whose last two coefficient
+    groups are not small enough for it; the full chains then score the queued
+    tiles again (or the whole batch once the queue overflows).  The batched
+    form always runs the full chains, so every template whose own tail is
+    large must match it bit for bit.  In "few_queued" the basis decays (groups
+    2 and 3 scaled by 1e-4 and 1e-7) and a handful of templates carry group-3
+    terms of up to ~100 bins, whose products of order 1 (left out by the
+    reduced chain) move positions by tenths of a bin; "all_queued" and
+    "queue_overflow" use a basis that does not decay, so every wave queues
+    (about 520 and 3100 queue entries against a capacity of 1024)."""
+    import torch
+    emri = gpu_lib
+    K = 16
+    g = np.random.default_rng({"few_queued": 81, "all_queued": 82, "queue_overflow": 83}[case])
+    n_seg, n_bins, t = {"few_queued": (40, 6000, 163840.0), "all_queued": (12, 3000, 163840.0),
+                        "queue_overflow": (9, 3000, 163840.0)}[case]
+    n = {"few_queued": 60000, "all_queued": 100000, "queue_overflow": 600000}[case]
+    P = g.exponential(size=(n_seg, n_bins))
+    spec = emri.spectrogram_from_power(P, t, "f16")
+    f0 = g.uniform(0.4, 0.6, n_seg) * n_bins / t
+    U = g.standard_normal((n_seg, K)) * (15.0 / t)
+    C = g.uniform(-3, 3, (n, K)).astype(np.float32)
+    bad = np.arange(n)
+    if case == "few_queued":
+        U[:, 8:12] *= 1e-4
+        U[:, 12:16] *= 1e-7
+        bad = np.array([0, 5, 2303, 2304, 31000, 45678, n - 1])
+        C[bad, 12:16] = g.uniform(-2e7, 2e7, (bad.size, 4)).astype(np.float32)
+    pb = emri.Problem(spec, _t(f0), _t(U), _t(C), top_k=50)
+    emri.BatchPlan([pb], K, precision="mixed").run()
+    torch.cuda.synchronize()
+    full = _np(pb.stat)
+    got = _score(emri, spec, f0, U, C, 50, precision="mixed")
+    assert np.array_equal(got["stat"][bad], full[bad])
+    if case == "few_queued":
+        # the other templates ran the reduced chain: within the mixed form's
+        # tolerance of the oracle, and nearly all equal to the full chains
+        assert np.mean(got["stat"] == full) >= 0.99
+        rows = np.concatenate([np.arange(0, n, 211), bad])
+        P_used = spec.power().cpu().numpy().astype(np.float64)
+        o = oracle.score_tracks(P_used, f0, U, C[rows], spec.t_sft, 0)
+        rel = np.abs(got["stat"][rows] - o["stat"]) / np.abs(o["stat"])
+        assert np.quantile(rel, 0.99) <= 2e-3
+    else:
+        assert np.array_equal(got["topk_idx"], _np(pb.topk_idx))
