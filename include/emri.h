@@ -182,7 +182,12 @@ int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tm
  * With precision EMRI_MIXED the positions are FP32 sums (see emri_precision):
  * a position within the FP32 error (~1e-4 bin at 10^3 bins) of a half-integer
  * can take the neighbouring bin, so a small share of templates carries one
- * moved bin.  With rescore_top = 1 (and top_k > 0) the call takes the
+ * moved bin.  Above K = 12 templates whose coefficients 8..15 carry little of
+ * the contraction (at most 2^-9 and 2^-17 of its bound for groups 8..11 and
+ * 12..15) skip the smallest split products of those groups, which moves a
+ * position by less than the FP32 rounding already present; the others are
+ * scored with every product.  The batched form always uses every product.
+ * With rescore_top = 1 (and top_k > 0) the call takes the
  * kc = min(n_tmpl, max(4 top_k, 64), 4096) best templates of the mixed
  * statistic, evaluates each again exactly as the plain path does (its FP64
  * statistic bit for bit, written into stat), and returns the best top_k of
