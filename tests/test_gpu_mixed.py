@@ -235,8 +235,9 @@ def test_mixed_rescore_top_matches_plain(gpu_lib, n_seg, n_bins, n_tmpl, K, top_
     assert np.max(np.abs(resc["topk_val"][:kk] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
 
 
-@pytest.mark.parametrize("case", ["few_queued", "all_queued", "queue_overflow"])
-def test_mixed_reduced_chain_queue(gpu_lib, case):
+@pytest.mark.parametrize("case,K", [("few_queued", 16), ("few_queued", 13), ("all_queued", 16),
+                                    ("queue_overflow", 16)])
+def test_mixed_reduced_chain_queue(gpu_lib, case, K):
     """Above K = 12 a standalone mixed call runs the reduced chain (order <= 1
     products for coefficients 8..11, the leading product alone for 12..15) and
     queues, per wave, the tiles holding a template whose last two coefficient
@@ -248,11 +249,11 @@ def test_mixed_reduced_chain_queue(gpu_lib, case):
     terms of up to ~100 bins, whose products of order 1 (left out by the
     reduced chain) move positions by tenths of a bin; "all_queued" and
     "queue_overflow" use a basis that does not decay, so every wave queues
-    (about 520 and 3100 queue entries against a capacity of 1024)."""
+    (about 520 and 3100 queue entries against a capacity of 1024).  K = 13
+    has a single coefficient in group 3."""
     import torch
     emri = gpu_lib
-    K = 16
-    g = np.random.default_rng({"few_queued": 81, "all_queued": 82, "queue_overflow": 83}[case])
+    g = np.random.default_rng({"few_queued": 81, "all_queued": 82, "queue_overflow": 83}[case] + K)
     n_seg, n_bins, t = {"few_queued": (40, 6000, 163840.0), "all_queued": (12, 3000, 163840.0),
                         "queue_overflow": (9, 3000, 163840.0)}[case]
     n = {"few_queued": 60000, "all_queued": 100000, "queue_overflow": 600000}[case]
@@ -264,9 +265,9 @@ def test_mixed_reduced_chain_queue(gpu_lib, case):
     bad = np.arange(n)
     if case == "few_queued":
         U[:, 8:12] *= 1e-4
-        U[:, 12:16] *= 1e-7
+        U[:, 12:] *= 1e-7
         bad = np.array([0, 5, 2303, 2304, 31000, 45678, n - 1])
-        C[bad, 12:16] = g.uniform(-2e7, 2e7, (bad.size, 4)).astype(np.float32)
+        C[bad, 12:] = g.uniform(-2e7, 2e7, (bad.size, K - 12)).astype(np.float32)
     pb = emri.Problem(spec, _t(f0), _t(U), _t(C), top_k=50)
     emri.BatchPlan([pb], K, precision="mixed").run()
     torch.cuda.synchronize()
