@@ -141,17 +141,19 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
 }
 
 // Reduced chain (RED, four coefficient groups only).  Above K = 12 the last
-// groups of an SVD basis carry little: over the one-year box at K = 16 the
-// bound sum_k |c_k| max_alpha |U T| of group 2 is at most 1.3e-3, and of
-// group 3 1.7e-6, of a template's whole bound.  The reduced chain keeps,
-// for group 2, the products of piece order <= 1 (c0 u0, c0 u1, c1 u0) and,
-// for group 3, c0 u0 alone: the terms left out are below 2^-16 (group 2)
-// and 2^-8 (group 3) of the group's bound, so for a template whose group
-// bounds are at most 2^-9 and 2^-17 of its whole bound (tail_small) they
-// change the position by less than about 2^-24.4 of that bound, one
-// rounding of the FP32 sum.  A wave of the reduced launch that holds a
-// template outside those limits (or a wild one) queues its tile, and a
-// second launch scores the queued tiles again with the full chains.
+// groups of an SVD basis carry little: in 2e6 draws from the one-year box at
+// K = 16 the bound sum_k |c_k| max_alpha |U T| of group 2 is at most 1.0e-3,
+// and of group 3 1.6e-6, of a template's whole bound.  The reduced chain
+// keeps, for group 2, the products of piece order <= 1 (c0 u0, c0 u1, c1 u0)
+// and, for group 3, c0 u0 alone.  Piece i of a value is at most 2^-8i of it,
+// so the terms left out are at most ~3 * 2^-16 (group 2) and ~2^-7 (group 3)
+// of the group's bound; for a template whose group bounds are at most 2^-9
+// and 2^-17 of its whole bound (tail_small) they move a position by at most
+// ~2.5 * 2^-24 of that bound, against up to 24 roundings of 2^-24 of their
+// partial sums in the full chains' FP32 accumulation.  A wave of the reduced
+// launch that holds a template outside those limits (or a wild one) queues
+// its tile, and a second launch scores the queued tiles again with the full
+// chains.
 template <int KG, bool RED>
 constexpr bool product_kept(int i) {
   const int p = i / KG, g = i % KG;            // pair (smallest first) and group
