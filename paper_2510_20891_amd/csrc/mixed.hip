@@ -66,17 +66,74 @@ __device__ __forceinline__ unsigned bf16_pair(float a, float b) {
 __device__ __forceinline__ float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
 
+// Coefficients of template j (zeros if not live), padded to whole groups.
+template <int K, int KG>
+__device__ __forceinline__ void load_coeffs(const ScoreParams &p, int64_t j, bool live, float (&cf)[4 * KG]) {
+#pragma unroll
+  for (int k = 0; k < 4 * KG; ++k) cf[k] = 0.0f;
+  if constexpr (K % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k += 4) {
+      const float4 v = live ? reinterpret_cast<const float4 *>(p.coeffs + (size_t)j * K)[k / 4]
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      cf[k] = v.x;
+      cf[k + 1] = v.y;
+      cf[k + 2] = v.z;
+      cf[k + 3] = v.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < K; ++k) cf[k] = live ? p.coeffs[(size_t)j * K + k] : 0.0f;
+  }
+}
+
+// The tests of one template from its coefficients and the bounds of prep:
+// wild if it could place a track at |x| >= 2^21 bins (huge or non-finite
+// values); above K = 12, tail_small if the reduced chain covers it.  The
+// reduced launch and the re-scoring of queued tiles take the same decisions
+// from the same values.
+template <int K, int KG>
+__device__ __forceinline__ void template_tests(const float (&cf)[4 * KG], const_dptr bnd, bool &wild,
+                                               bool &tail_small) {
+  // every operation rounded on its own (no fused multiply-add), so that
+  // each inlined copy takes the same decision
+#pragma clang fp contract(off)
+  // the bound in FP32: K + 1 terms, each rounded at most three times
+  // (bound, product, sum), stay within 3 (K + 1) 2^-24 < 1e-5 of the exact
+  // sum, so b < 2^21 (1 - 1e-5) implies the exact bound is below 2^21; then
+  // |I + D| < 2^22 and the FP32 rounding of D + M is exact
+  float b = (float)bnd[0];
+  float bg[KG];
+#pragma unroll
+  for (int g = 0; g < KG; ++g) bg[g] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const float t = __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
+    b += t;
+    bg[k / 4] += t;
+  }
+  wild = !(b < 2097152.0f * 0.99999f);
+  tail_small = true;
+  if constexpr (KG == 4) {
+    // the reduced chain's limits, less a margin of 1 % for the FP32
+    // rounding of these sums (non-finite values fail the test)
+    const float all = bg[0] + bg[1] + bg[2] + bg[3];
+    tail_small = bg[2] <= 0x1p-9f * 0.99f * all && bg[3] <= 0x1p-17f * 0.99f * all;
+  }
+}
+
 // Load and split the coefficients of this lane's TPL templates of tile t0.
 // Returns true if any of them could place a track at |x| >= 2^21 bins (huge
-// or non-finite values), from the per-segment bounds of prep.
+// or non-finite values), from the per-segment bounds of prep.  Above K = 12,
+// needs_full is true if any of them needs the full chains (template_tests:
+// wild, or not covered by the reduced chain).
 template <int K, int KG, int TPL>
 __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, int64_t j_end, Pieces<KG, TPL> &pc,
-                                            bool &tail_small) {
+                                            bool &needs_full) {
   const int tid = threadIdx.x;
-  typedef const __attribute__((address_space(4))) double *const_dptr;
   const_dptr bnd = (const_dptr)p.bound;
   bool wild = false;
-  tail_small = true;
+  needs_full = false;
 #pragma unroll
   for (int s = 0; s < TPL; ++s) {
     const int64_t j = t0 + (int64_t)s * mixed_threads(K) + tid;
@@ -103,21 +160,13 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
     // sum, so b < 2^21 (1 - 1e-5) implies the exact bound is below 2^21; then
     // |I + D| < 2^22 and the FP32 rounding of D + M is exact
     float b = (float)bnd[0];
-    float bg[KG];
 #pragma unroll
-    for (int g = 0; g < KG; ++g) bg[g] = 0.0f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const float t = __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
-      b += t;
-      bg[k / 4] += t;
-    }
+    for (int k = 0; k < K; ++k) b += __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
     wild |= !(b < 2097152.0f * 0.99999f);
     if constexpr (KG == 4) {
-      // the reduced chain's limits, less a margin of 1 % for the FP32
-      // rounding of these sums (non-finite values fail the test)
-      const float all = bg[0] + bg[1] + bg[2] + bg[3];
-      tail_small &= bg[2] <= 0x1p-9f * 0.99f * all && bg[3] <= 0x1p-17f * 0.99f * all;
+      bool wild_s, tail_small;
+      template_tests<K, KG>(cf, bnd, wild_s, tail_small);
+      needs_full |= wild_s || !tail_small;
     }
 #pragma unroll
     for (int g = 0; g < KG; ++g) {
@@ -153,7 +202,7 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
 // partial sums in the full chains' FP32 accumulation.  A wave of the reduced
 // launch that holds a template outside those limits (or a wild one) queues
 // its tile, and a second launch scores the queued tiles again with the full
-// chains.
+// chains, which write the statistics of the templates that need them.
 template <int KG, bool RED>
 constexpr bool product_kept(int i) {
   const int p = i / KG, g = i % KG;            // pair (smallest first) and group
@@ -448,7 +497,11 @@ __device__ __forceinline__ unsigned char *staging_base(const ScoreParams &p, uns
   return lds + ((p.mtab_bytes + 1023) & ~1023);
 }
 
-template <int K, int T, typename PT, bool RED>
+// RED: the reduced chain, queueing the tile when a template needs the full
+// ones; ONLY_FULL: the full chains, writing only the statistics of the
+// templates that need them (the re-scoring of queued tiles), so that every
+// statistic depends on its own template alone, not on its tile-mates.
+template <int K, int T, typename PT, bool RED, bool ONLY_FULL = false>
 __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned char *lds, unsigned char *stage,
                                                  int64_t t0, int64_t j_end) {
   constexpr int KG = (K + 3) / 4;
@@ -463,8 +516,8 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
     if (pp.wave < SCORE_WAVES) pipe_issue(p, pp, stage, 0, 0);
   }
   Pieces<KG, T> pc;
-  bool tail_small;
-  const bool wild = load_pieces<K, KG, T>(p, t0, j_end, pc, tail_small);
+  bool needs_full;
+  const bool wild = load_pieces<K, KG, T>(p, t0, j_end, pc, needs_full);
   double sum[T];
 #pragma unroll
   for (int s = 0; s < T; ++s) sum[s] = 0.0;
@@ -472,7 +525,7 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
     // one chain only: a wave holding a template it does not cover queues the
     // tile for the full chains (waves of one tile may queue it more than once;
     // the full chains then write the same values again)
-    if (__any(wild || !tail_small) && (threadIdx.x & 63) == 0) {
+    if (__any(needs_full) && (threadIdx.x & 63) == 0) {
       const unsigned e = atomicAdd(p.redo, 1u);
       const int64_t t_end = t0 + (int64_t)T * mixed_threads(K) < j_end ? t0 + (int64_t)T * mixed_threads(K) : j_end;
       if (e < (unsigned)MIXED_REDO_CAP)
@@ -487,12 +540,22 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
 #pragma unroll
   for (int s = 0; s < T; ++s) {
     const int64_t j = t0 + (int64_t)s * mixed_threads(K) + threadIdx.x;
-    if (j < j_end) p.stat[j] = (float)sum[s];
+    bool write = j < j_end;
+    if constexpr (ONLY_FULL) {
+      // the template's tests again (its coefficients are read once more,
+      // rather than a mask kept live through the tile)
+      float cf[4 * KG];
+      load_coeffs<K, KG>(p, j, write, cf);
+      bool wild_s, tail_small;
+      template_tests<K, KG>(cf, (const_dptr)p.bound, wild_s, tail_small);
+      write = write && (wild_s || !tail_small);
+    }
+    if (write) p.stat[j] = (float)sum[s];
   }
 }
 
 // Tiles of TPL slots; a last tile that fits in half as many slots runs with half.
-template <int K, int TPL, typename PT, bool RED = false>
+template <int K, int TPL, typename PT, bool RED = false, bool ONLY_FULL = false>
 __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned char *lds, int64_t j_begin,
                                                   int64_t j_end) {
   constexpr int TAIL = (TPL + 1) / 2;
@@ -500,10 +563,10 @@ __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned
   constexpr int NT = mixed_threads(K);
   for (int64_t t0 = j_begin; t0 < j_end; t0 += (int64_t)TPL * NT) {
     if (TAIL < TPL && j_end - t0 <= (int64_t)TAIL * NT) {
-      score_tile_mixed<K, TAIL, PT, RED>(p, lds, stage, t0, j_end);
+      score_tile_mixed<K, TAIL, PT, RED, ONLY_FULL>(p, lds, stage, t0, j_end);
       break;
     }
-    score_tile_mixed<K, TPL, PT, RED>(p, lds, stage, t0, j_end);
+    score_tile_mixed<K, TPL, PT, RED, ONLY_FULL>(p, lds, stage, t0, j_end);
   }
 }
 
@@ -511,7 +574,8 @@ __device__ __forceinline__ void score_range_mixed(const ScoreParams &p, unsigned
 // chain (queues the tiles it does not cover in p.redo); MODE 2: the full
 // chains over the tiles the reduced launch queued (grid-strided; nothing if
 // the queue overflowed); MODE 3: the full chains over the workgroup's range
-// if the queue overflowed (nothing otherwise).
+// if the queue overflowed (nothing otherwise).  Modes 2 and 3 write only the
+// statistics of the templates that need the full chains.
 template <int K, int TPL, typename PT, int MODE>
 __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScoreParams p) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -525,7 +589,7 @@ __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScorePara
       const uint2 *q = reinterpret_cast<const uint2 *>(p.redo + 4);
       for (unsigned e = blockIdx.x; e < n_redo; e += gridDim.x) {
         const uint2 t = q[e];
-        score_tile_mixed<K, TPL, PT, false>(p, lds, staging_base(p, lds), (int64_t)t.x, (int64_t)t.y);
+        score_tile_mixed<K, TPL, PT, false, true>(p, lds, staging_base(p, lds), (int64_t)t.x, (int64_t)t.y);
       }
       return;
     }
@@ -534,7 +598,7 @@ __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScorePara
   init_lds(p, staging_base(p, lds));
   const int64_t j_begin = (int64_t)blockIdx.x * p.per_block;
   const int64_t j_end = j_begin + p.per_block < p.n_tmpl ? j_begin + p.per_block : p.n_tmpl;
-  score_range_mixed<K, TPL, PT, MODE == 1>(p, lds, j_begin, j_end);
+  score_range_mixed<K, TPL, PT, MODE == 1, MODE == 3>(p, lds, j_begin, j_end);
 }
 
 // Batched form of the mixed kernel (work items claimed as in the plain

@@ -250,7 +250,10 @@ def test_mixed_reduced_chain_queue(gpu_lib, case, K):
     reduced chain) move positions by tenths of a bin; "all_queued" and
     "queue_overflow" use a basis that does not decay, so every wave queues
     (about 520 and 3100 queue entries against a capacity of 1024).  K = 13
-    has a single coefficient in group 3."""
+    has a single coefficient in group 3.  The re-scoring writes only the
+    templates that need the full chains, so a statistic does not depend on
+    the template's tile-mates: a call on a slice of the batch (other tiles)
+    returns the same statistics bit for bit."""
     import torch
     emri = gpu_lib
     g = np.random.default_rng({"few_queued": 81, "all_queued": 82, "queue_overflow": 83}[case] + K)
@@ -283,5 +286,7 @@ def test_mixed_reduced_chain_queue(gpu_lib, case, K):
         o = oracle.score_tracks(P_used, f0, U, C[rows], spec.t_sft, 0)
         rel = np.abs(got["stat"][rows] - o["stat"]) / np.abs(o["stat"])
         assert np.quantile(rel, 0.99) <= 2e-3
+        sub = _score(emri, spec, f0, U, C[1000:], 0, precision="mixed")
+        assert np.array_equal(sub["stat"], got["stat"][1000:])
     else:
         assert np.array_equal(got["topk_idx"], _np(pb.topk_idx))
