@@ -188,7 +188,8 @@ int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tm
  * position by at most 2.5 * 2^-24 of the contraction bound (the FP32
  * accumulation of the full products already rounds 24 times by up to 2^-24
  * of its partial sums); the others are scored with every product.  Either
- * way a statistic depends on its own template only.  The batched form always uses every product.
+ * way a statistic depends on its own template only, and the batched form
+ * (score_batched_run) returns the same statistics bit for bit.
  * With rescore_top = 1 (and top_k > 0) the call takes the
  * kc = min(n_tmpl, max(4 top_k, 64), 4096) best templates of the mixed
  * statistic, evaluates each again exactly as the plain path does (its FP64

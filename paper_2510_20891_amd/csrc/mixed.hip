@@ -529,7 +529,7 @@ __device__ __forceinline__ void score_tile_mixed(const ScoreParams &p, unsigned 
       const unsigned e = atomicAdd(p.redo, 1u);
       const int64_t t_end = t0 + (int64_t)T * mixed_threads(K) < j_end ? t0 + (int64_t)T * mixed_threads(K) : j_end;
       if (e < (unsigned)MIXED_REDO_CAP)
-        reinterpret_cast<uint2 *>(p.redo + 4)[e] = make_uint2((unsigned)t0, (unsigned)t_end);
+        reinterpret_cast<uint4 *>(p.redo + 4)[e] = make_uint4((unsigned)t0, (unsigned)t_end, p.redo_tag, 0u);
     }
     run_tile_mixed<KG, T, PT, false, true>(p, &pp, lds, stage, pc, sum);
   } else if (__any(wild)) {
@@ -586,9 +586,9 @@ __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScorePara
     if constexpr (MODE == 2) {
       load_table<mixed_threads(K)>(p, lds);
       init_lds(p, staging_base(p, lds));
-      const uint2 *q = reinterpret_cast<const uint2 *>(p.redo + 4);
+      const uint4 *q = reinterpret_cast<const uint4 *>(p.redo + 4);
       for (unsigned e = blockIdx.x; e < n_redo; e += gridDim.x) {
-        const uint2 t = q[e];
+        const uint4 t = q[e];
         score_tile_mixed<K, TPL, PT, false, true>(p, lds, staging_base(p, lds), (int64_t)t.x, (int64_t)t.y);
       }
       return;
@@ -603,12 +603,21 @@ __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_kernel(ScorePara
 
 // Batched form of the mixed kernel (work items claimed as in the plain
 // batched kernel; the piece table is reloaded when the stream changes).
-template <int K, int TPL, typename PT>
+// MODE as in score_mixed_kernel: 0 the full chains, 1 the reduced chain
+// (queueing tiles tagged with their problem), 3 the full chains over every
+// item, writing only the templates that need them, if the queue overflowed
+// (claims from counter[1]; nothing otherwise).
+template <int K, int TPL, typename PT, int MODE>
 __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_batched_kernel(const ScoreParams *__restrict__ params,
                                                                             const BatchItem *__restrict__ items,
-                                                                            int n_items, int *counter) {
+                                                                            int n_items, int *counter,
+                                                                            const unsigned *redo) {
   extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
   __shared__ int slot;
+  if constexpr (MODE == 3) {
+    if (__builtin_amdgcn_readfirstlane(*(const volatile unsigned *)redo) <= (unsigned)MIXED_REDO_CAP) return;
+    counter += 1;
+  }
   int table_of = -1;
   for (;;) {
     const int it = claim_item(counter, &slot);
@@ -620,7 +629,31 @@ __global__ __launch_bounds__(mixed_threads(K)) void score_mixed_batched_kernel(c
       table_of = item.stream;
     }
     init_lds(p, staging_base(p, lds));
-    score_range_mixed<K, TPL, PT>(p, lds, item.begin, item.end);
+    score_range_mixed<K, TPL, PT, MODE == 1, MODE == 3>(p, lds, item.begin, item.end);
+  }
+}
+
+// The queued tiles of a batched reduced-chain launch, with the full chains
+// (each entry names its problem; grid-strided; nothing if the queue
+// overflowed), writing only the templates that need them.
+template <int K, int TPL, typename PT>
+__global__ __launch_bounds__(mixed_threads(K)) void score_mixed_requeue_kernel(const ScoreParams *__restrict__ params,
+                                                                            const unsigned *redo) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+  const unsigned n_redo = __builtin_amdgcn_readfirstlane(*(const volatile unsigned *)redo);
+  if (n_redo > (unsigned)MIXED_REDO_CAP || blockIdx.x >= n_redo) return;
+  const uint4 *q = reinterpret_cast<const uint4 *>(redo + 4);
+  int table_of = -1;
+  for (unsigned e = blockIdx.x; e < n_redo; e += gridDim.x) {
+    const uint4 t = q[e];
+    const ScoreParams p = load_uniform(params + t.z);
+    __syncthreads();                   // every wave is done with the previous tile's LDS
+    if ((int)t.z != table_of) {
+      load_table<mixed_threads(K)>(p, lds);
+      table_of = (int)t.z;
+    }
+    init_lds(p, staging_base(p, lds));
+    score_tile_mixed<K, TPL, PT, false, true>(p, lds, staging_base(p, lds), (int64_t)t.x, (int64_t)t.y);
   }
 }
 
@@ -666,13 +699,38 @@ hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_
   return launch_mixed_mode<K, PT, 0>(p, grid, lds, stream);
 }
 
-template <int K, typename PT>
-hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
-  auto kern = score_mixed_batched_kernel<K, mixed_tpl(K), PT>;
+template <int K, typename PT, int MODE>
+hipError_t launch_mixed_batched_mode(const BatchLaunch &b, hipStream_t stream) {
+  auto kern = score_mixed_batched_kernel<K, mixed_tpl(K), PT, MODE>;
   hipError_t err = set_lds(kern, b.lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(mixed_threads(K)), b.lds, stream, b.params, b.items, b.n_items, b.counter);
+  hipLaunchKernelGGL(kern, dim3(b.grid), dim3(mixed_threads(K)), b.lds, stream, b.params, b.items, b.n_items, b.counter,
+                     (const unsigned *)b.redo);
   return hipGetLastError();
+}
+
+// Above K = 12 (with a tile queue in b.redo, whose count the prep kernel of
+// the run cleared): the reduced chain over every item, the full chains over
+// the queued tiles, then over every item only if the queue overflowed.
+template <int K, typename PT>
+hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
+  if constexpr (mixed_groups(K) == 4) {
+    if (b.redo) {
+      hipError_t err = launch_mixed_batched_mode<K, PT, 1>(b, stream);
+      if (err == hipSuccess) {
+        auto kern = score_mixed_requeue_kernel<K, mixed_tpl(K), PT>;
+        err = set_lds(kern, b.lds);
+        if (err == hipSuccess) {
+          hipLaunchKernelGGL(kern, dim3(b.grid), dim3(mixed_threads(K)), b.lds, stream, b.params,
+                             (const unsigned *)b.redo);
+          err = hipGetLastError();
+        }
+      }
+      if (err == hipSuccess) err = launch_mixed_batched_mode<K, PT, 3>(b, stream);
+      return err;
+    }
+  }
+  return launch_mixed_batched_mode<K, PT, 0>(b, stream);
 }
 
 template <typename PT, int... Ks>

@@ -474,7 +474,9 @@ __global__ __launch_bounds__(256) void score_prep_kernel(PrepJob job) {
 // Problem blockIdx.x: workgroup y = 0 computes its constants, the others
 // reset a share of its top-k state each.
 __global__ __launch_bounds__(256) void score_prep_batched_kernel(const PrepJob *__restrict__ jobs, int *counter) {
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *counter = 0;   // work items of the scoring launch
+  // work items of the scoring launch, and of the mixed form's full-chain
+  // launch after a queue overflow
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;
   const PrepJob job = load_uniform(jobs + blockIdx.x);
   if (blockIdx.y > 0) {
     if (job.topk) topk_state_reset(job.topk, blockIdx.y - 1, gridDim.y - 1);

@@ -43,7 +43,7 @@ struct ScoreParams {
   // pass the scoring workgroups run over their own statistics, or null
   TopkState *topk;
   uint32_t topk_kk;           // min(n_tmpl, top_k)
-  uint32_t pad2;
+  uint32_t redo_tag;          // recorded with each queued tile: the problem of a batched launch (0 otherwise)
 };
 
 // Mixed-precision form: per-segment offset f0*T = I + phi with I the even
@@ -58,11 +58,12 @@ struct MixedSeg {
 
 constexpr int MIXED_MAX_K = 16;
 // Queue of tiles the reduced-chain mixed launch leaves to the full chains:
-// word 0 counts the entries claimed; entry e, a pair of 32-bit words (first
-// template, end of the tile), starts at byte 16 + 8e.  A count above the
-// capacity sends the whole batch to the full chains.
+// word 0 counts the entries claimed; entry e, four 32-bit words (first
+// template, end of the tile, the queueing launch's redo_tag, unused), starts
+// at byte 16 + 16e.  A count above the capacity sends the whole batch to the
+// full chains.
 constexpr int MIXED_REDO_CAP = 1024;
-constexpr size_t MIXED_REDO_BYTES = 16 + 8 * (size_t)MIXED_REDO_CAP;
+constexpr size_t MIXED_REDO_BYTES = 16 + 16 * (size_t)MIXED_REDO_CAP;
 // Workgroup size of the mixed kernel: 1024 threads (four waves per SIMD, 128
 // VGPRs each) up to K = 8, 768 (three waves, 168 VGPRs) above; the first
 // SCORE_WAVES of its waves stage the rows.
@@ -102,10 +103,11 @@ struct PrepJob {
 struct BatchLaunch {
   const ScoreParams *params;
   const BatchItem *items;
-  int *counter;               // next item to claim (reset to 0 by the prep kernel of each run)
+  int *counter;               // next item to claim, [0] and [1] (reset to 0 by the prep kernel of each run)
   int n_items, grid, K, dtype, tpl;
   int mixed;
   size_t lds;
+  unsigned *redo;             // mixed above K = 12: the tile queue of the reduced-chain launch, or null
 };
 
 // Read a small trivially copyable struct from read-only device memory with
