@@ -182,7 +182,7 @@ int score_tracks_workspace_size(const emri_power *power, int32_t K, int64_t n_tm
  * With precision EMRI_MIXED the positions are FP32 sums (see emri_precision):
  * a position within the FP32 error (~1e-4 bin at 10^3 bins) of a half-integer
  * can take the neighbouring bin, so a small share of templates carries one
- * moved bin.  Above K = 12 templates whose coefficients 8..15 carry little of
+ * moved bin.  Above K = 8 templates whose coefficients 8..15 carry little of
  * the contraction (at most 2^-9 and 2^-17 of its bound for groups 8..11 and
  * 12..15) skip the smallest split products of those groups, which moves a
  * position by at most 2.5 * 2^-24 of the contraction bound (the FP32

@@ -252,7 +252,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
     if (mixed) {
       job.mtab = ws + L.mtab_off;
       job.mseg = ws + L.mseg_off;
-      if (K > 12) job.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
+      if (K > 8) job.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
     }
     if (top_k > 0) job.topk = reinterpret_cast<TopkState *>(ws + L.topk_off);
     err = launch_score_prep(job, stream);
@@ -281,7 +281,7 @@ int score_tracks_impl(const emri_power *power, const double *f0, const double *U
       p.mtab = ws + L.mtab_off;
       p.mseg = ws + L.mseg_off;
       p.mtab_bytes = mtab_bytes;
-      if (K > 12) p.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
+      if (K > 8) p.redo = reinterpret_cast<unsigned *>(ws + L.redo_off);
     }
     // a plain launch with a top-k also runs the top-k's first key pass
     size_t lds = sg.lds;

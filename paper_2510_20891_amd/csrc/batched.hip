@@ -91,7 +91,7 @@ Layout make_layout(const emri_problem *pbs, int n, int K, int64_t max_items) {
   L.topk_blocks = take(sizeof(int32_t) * (size_t)topk_max_blocks(topk_n.data(), (int)topk_n.size()));
   L.items = take(sizeof(BatchItem) * (size_t)max_items);
   L.counter = take(2 * sizeof(int));
-  L.redo = take(MIXED_REDO_BYTES);   // the mixed form's tile queue above K = 12
+  L.redo = take(MIXED_REDO_BYTES);   // the mixed form's tile queue above K = 8
   L.seg = off;
   for (int i = 0; i < n; ++i) {
     const int ns = pbs[i].power.n_seg > 0 ? pbs[i].power.n_seg : 1;
@@ -253,7 +253,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
       p.mtab = ws + L.mtab_off[i];
       p.mseg = ws + L.mseg_off[i];
       p.mtab_bytes = ((pb.power.n_seg + 3) & ~3) * mixed_row_bytes(K);
-      if (K > 12) p.redo = reinterpret_cast<unsigned *>(ws + L.redo);
+      if (K > 8) p.redo = reinterpret_cast<unsigned *>(ws + L.redo);
       p.redo_tag = (uint32_t)i;
     }
     PrepJob &pj = preps[i];
@@ -269,7 +269,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
     if (mixed) {
       pj.mtab = ws + L.mtab_off[i];
       pj.mseg = ws + L.mseg_off[i];
-      if (K > 12 && i == 0) pj.redo = reinterpret_cast<unsigned *>(ws + L.redo);   // clears the queue's count
+      if (K > 8 && i == 0) pj.redo = reinterpret_cast<unsigned *>(ws + L.redo);   // clears the queue's count
     }
     if (pb.top_k > 0) {
       pj.topk = reinterpret_cast<TopkState *>(ws + L.topk_off[i]);
@@ -345,7 +345,7 @@ extern "C" int score_batched_plan(const emri_problem *problems, int32_t n_proble
   pd.launch.tpl = tpl;
   pd.launch.lds = lds;
   pd.launch.mixed = mixed ? 1 : 0;
-  pd.launch.redo = (mixed && K > 12) ? reinterpret_cast<unsigned *>(ws + L.redo) : nullptr;
+  pd.launch.redo = (mixed && K > 8) ? reinterpret_cast<unsigned *>(ws + L.redo) : nullptr;
   pd.prep_jobs = reinterpret_cast<const PrepJob *>(ws + L.prep);
   pd.topk_jobs = reinterpret_cast<const TopkJob *>(ws + L.topk_jobs);
   pd.topk_block_job = reinterpret_cast<const int32_t *>(ws + L.topk_blocks);

@@ -89,7 +89,7 @@ __device__ __forceinline__ void load_coeffs(const ScoreParams &p, int64_t j, boo
 
 // The tests of one template from its coefficients and the bounds of prep:
 // wild if it could place a track at |x| >= 2^21 bins (huge or non-finite
-// values); above K = 12, tail_small if the reduced chain covers it.  The
+// values); above K = 8, tail_small if the reduced chain covers it.  The
 // reduced launch and the re-scoring of queued tiles take the same decisions
 // from the same values.
 template <int K, int KG>
@@ -114,17 +114,20 @@ __device__ __forceinline__ void template_tests(const float (&cf)[4 * KG], const_
   }
   wild = !(b < 2097152.0f * 0.99999f);
   tail_small = true;
-  if constexpr (KG == 4) {
+  if constexpr (KG >= 3) {
     // the reduced chain's limits, less a margin of 1 % for the FP32
     // rounding of these sums (non-finite values fail the test)
-    const float all = bg[0] + bg[1] + bg[2] + bg[3];
-    tail_small = bg[2] <= 0x1p-9f * 0.99f * all && bg[3] <= 0x1p-17f * 0.99f * all;
+    float all = 0.0f;
+#pragma unroll
+    for (int g = 0; g < KG; ++g) all += bg[g];
+    tail_small = bg[2] <= 0x1p-9f * 0.99f * all;
+    if constexpr (KG == 4) tail_small = tail_small && bg[3] <= 0x1p-17f * 0.99f * all;
   }
 }
 
 // Load and split the coefficients of this lane's TPL templates of tile t0.
 // Returns true if any of them could place a track at |x| >= 2^21 bins (huge
-// or non-finite values), from the per-segment bounds of prep.  Above K = 12,
+// or non-finite values), from the per-segment bounds of prep.  Above K = 8,
 // needs_full is true if any of them needs the full chains (template_tests:
 // wild, or not covered by the reduced chain).
 template <int K, int KG, int TPL>
@@ -163,7 +166,7 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
 #pragma unroll
     for (int k = 0; k < K; ++k) b += __builtin_fabsf(cf[k]) * (float)bnd[1 + k];
     wild |= !(b < 2097152.0f * 0.99999f);
-    if constexpr (KG == 4) {
+    if constexpr (KG >= 3) {
       bool wild_s, tail_small;
       template_tests<K, KG>(cf, bnd, wild_s, tail_small);
       needs_full |= wild_s || !tail_small;
@@ -189,16 +192,17 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
   return wild;
 }
 
-// Reduced chain (RED, four coefficient groups only).  Above K = 12 the last
-// groups of an SVD basis carry little: in 2e6 draws from the one-year box at
-// K = 16 the bound sum_k |c_k| max_alpha |U T| of group 2 is at most 1.0e-3,
-// and of group 3 1.6e-6, of a template's whole bound.  The reduced chain
-// keeps, for group 2, the products of piece order <= 1 (c0 u0, c0 u1, c1 u0)
-// and, for group 3, c0 u0 alone.  Piece i of a value is at most 2^-8i of it,
-// so the terms left out are at most ~3 * 2^-16 (group 2) and ~2^-7 (group 3)
-// of the group's bound; for a template whose group bounds are at most 2^-9
-// and 2^-17 of its whole bound (tail_small) they move a position by at most
-// ~2.5 * 2^-24 of that bound, against up to 24 roundings of 2^-24 of their
+// Reduced chain (RED, three or four coefficient groups).  Above K = 8 the
+// last groups of an SVD basis carry little: in draws from the one-year box
+// the bound sum_k |c_k| max_alpha |U T| of group 2 is at most 1.0e-3 of a
+// template's whole bound (K = 9 .. 16), and of group 3 1.6e-6 (K = 16).  The
+// reduced chain keeps, for group 2, the products of piece order <= 1
+// (c0 u0, c0 u1, c1 u0) and, for group 3, c0 u0 alone.  Piece i of a value
+// is at most 2^-8i of it, so the terms left out are at most ~3 * 2^-16
+// (group 2) and ~2^-7 (group 3) of the group's bound; for a template whose
+// group bounds are at most 2^-9 and 2^-17 of its whole bound (tail_small)
+// they move a position by at most ~2.5 * 2^-24 of that bound (~1.5 * 2^-24
+// with three groups), against up to 18 or 24 roundings of 2^-24 of their
 // partial sums in the full chains' FP32 accumulation.  A wave of the reduced
 // launch that holds a template outside those limits (or a wild one) queues
 // its tile, and a second launch scores the queued tiles again with the full
@@ -206,7 +210,7 @@ __device__ __forceinline__ bool load_pieces(const ScoreParams &p, int64_t t0, in
 template <int KG, bool RED>
 constexpr bool product_kept(int i) {
   const int p = i / KG, g = i % KG;            // pair (smallest first) and group
-  return !RED || !((g == KG - 2 && p < 3) || (g == KG - 1 && p < 5));
+  return !RED || !((g == 2 && p < 3) || (g == 3 && p < 5));
 }
 template <int KG, bool RED>
 constexpr int products_in_part(int part) {
@@ -682,13 +686,13 @@ hipError_t launch_mixed_mode(const ScoreParams &p, int grid, size_t lds, hipStre
   return hipGetLastError();
 }
 
-// Above K = 12 (with a tile queue in p.redo, whose count the prep kernel of
+// Above K = 8 (with a tile queue in p.redo, whose count the prep kernel of
 // the call cleared): the reduced launch, then the full chains over the tiles
 // it queued (workgroups past the queue's length return at once), then over
 // the whole batch only if the queue overflowed.
 template <int K, typename PT>
 hipError_t launch_mixed_k(const ScoreParams &p, int grid, size_t lds, hipStream_t stream) {
-  if constexpr (mixed_groups(K) == 4) {
+  if constexpr (mixed_groups(K) >= 3) {
     if (p.redo) {
       hipError_t err = launch_mixed_mode<K, PT, 1>(p, grid, lds, stream);
       if (err == hipSuccess) err = launch_mixed_mode<K, PT, 2>(p, grid, lds, stream);
@@ -709,12 +713,12 @@ hipError_t launch_mixed_batched_mode(const BatchLaunch &b, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Above K = 12 (with a tile queue in b.redo, whose count the prep kernel of
+// Above K = 8 (with a tile queue in b.redo, whose count the prep kernel of
 // the run cleared): the reduced chain over every item, the full chains over
 // the queued tiles, then over every item only if the queue overflowed.
 template <int K, typename PT>
 hipError_t launch_mixed_batched_k(const BatchLaunch &b, hipStream_t stream) {
-  if constexpr (mixed_groups(K) == 4) {
+  if constexpr (mixed_groups(K) >= 3) {
     if (b.redo) {
       hipError_t err = launch_mixed_batched_mode<K, PT, 1>(b, stream);
       if (err == hipSuccess) {

@@ -37,7 +37,7 @@ struct ScoreParams {
   const void *mseg;           // per segment: MixedSeg
   int mtab_bytes;             // bytes of mtab for round_up(n_seg, 4) segments (staged in LDS first)
   float one;                  // 1.0f: FP16 power is added as fma(P, one, acc), one instruction
-  unsigned *redo;             // above K = 12: the reduced-chain launch's queue of tiles for the
+  unsigned *redo;             // above K = 8: the reduced-chain launch's queue of tiles for the
                               // full chains (MIXED_REDO_BYTES; count cleared by the prep kernel), or null
   // standalone plain launches with a top-k: the top-k state whose first key
   // pass the scoring workgroups run over their own statistics, or null
@@ -107,7 +107,7 @@ struct BatchLaunch {
   int n_items, grid, K, dtype, tpl;
   int mixed;
   size_t lds;
-  unsigned *redo;             // mixed above K = 12: the tile queue of the reduced-chain launch, or null
+  unsigned *redo;             // mixed above K = 8: the tile queue of the reduced-chain launch, or null
 };
 
 // Read a small trivially copyable struct from read-only device memory with

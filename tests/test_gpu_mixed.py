@@ -235,10 +235,11 @@ def test_mixed_rescore_top_matches_plain(gpu_lib, n_seg, n_bins, n_tmpl, K, top_
     assert np.max(np.abs(resc["topk_val"][:kk] - o["stat"]) / np.maximum(o["stat"], 1e-30)) <= 1e-5
 
 
-@pytest.mark.parametrize("case,K", [("few_queued", 16), ("few_queued", 13), ("all_queued", 16),
+@pytest.mark.parametrize("case,K", [("few_queued", 16), ("few_queued", 13), ("few_queued", 12),
+                                    ("few_queued", 9), ("all_queued", 16), ("all_queued", 12),
                                     ("queue_overflow", 16)])
 def test_mixed_reduced_chain_queue(gpu_lib, case, K):
-    """Above K = 12 the mixed form runs the reduced chain (order <= 1 products
+    """Above K = 8 the mixed form runs the reduced chain (order <= 1 products
     for coefficients 8..11, the leading product alone for 12..15) and queues,
     per wave, the tiles holding a template whose last two coefficient groups
     are not small enough for it; the full chains then score the queued tiles
@@ -248,12 +249,14 @@ def test_mixed_reduced_chain_queue(gpu_lib, case, K):
     standalone calls bit for bit, as does a call on a slice of the batch
     (other tiles).  In "few_queued" the basis decays (groups 2 and 3 scaled
     by 1e-4 and 1e-7) and a handful of templates carry group-3 terms of up to
-    ~450 bins per coefficient, whose products of order 1 (left out by the
-    reduced chain) move positions by whole bins: those templates must match
-    the FP64 oracle to 1e-6 wherever no position lies within 1e-3 bin of a
-    half-integer.  "all_queued" and "queue_overflow" use a basis that does
+    ~450 bins per coefficient (K > 12; left-out products of order 1 move
+    positions by whole bins) or group-2 terms of up to ~225 bins (K <= 12;
+    left-out products of order 2 move them by a few hundredths): those
+    templates must match the FP64 oracle to 1e-6 wherever no position lies
+    within 1e-3 bin of a half-integer.  "all_queued" and "queue_overflow" use a basis that does
     not decay, so every wave queues (about 520 and 3100 queue entries
-    against a capacity of 1024).  K = 13 has a single coefficient in group 3."""
+    against a capacity of 1024).  K = 13 has a single coefficient in group 3,
+    K = 9 a single one in group 2."""
     import torch
     emri = gpu_lib
     g = np.random.default_rng({"few_queued": 81, "all_queued": 82, "queue_overflow": 83}[case] + K)
@@ -269,7 +272,10 @@ def test_mixed_reduced_chain_queue(gpu_lib, case, K):
         U[:, 8:12] *= 1e-4
         U[:, 12:] *= 1e-7
         bad = np.array([0, 5, 2303, 2304, 31000, 45678, n - 1])
-        C[bad, 12:] = g.uniform(-1e8, 1e8, (bad.size, K - 12)).astype(np.float32)
+        if K > 12:
+            C[bad, 12:] = g.uniform(-1e8, 1e8, (bad.size, K - 12)).astype(np.float32)
+        else:
+            C[bad, 8:] = g.uniform(-5e4, 5e4, (bad.size, K - 8)).astype(np.float32)
     pb = emri.Problem(spec, _t(f0), _t(U), _t(C), top_k=50)
     emri.BatchPlan([pb], K, precision="mixed").run()
     torch.cuda.synchronize()
